@@ -1,0 +1,270 @@
+"""FP64 reference oracle (test infrastructure only).
+
+This package is the checker that the GPU library is graded against.  Only
+the test suite, the smoke check and the CPU-baseline leg of the benchmark
+import it; the GPU library never does, and the two share no code.
+
+The compiled part (``oracle.c``) computes every result from its plain
+definition: brute force over all (query, point) pairs in double precision,
+starting from the same FP32 arrays the GPU receives.  The normalisation
+helpers below (RDF, PMF, PMFT, smoothed RDF) are closed-form FP64 numpy.
+
+Each function names the part of the paper it follows.  Parity status:
+  * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts,
+    smoothed RDF and its gradient: pinned (see tests/test_oracle_*.py);
+  * RDF / PMFT normalisation constants: the paper defines the PMF and PMFT
+    only up to an additive constant, so the convention below is a reading,
+    pinned statistically by the ideal-gas limit only.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+REL_BAND = 1e-5  # ambiguity band, relative in r^2, for cutoff and bin edges
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("tilt", ctypes.c_double * 3), ("dim", ctypes.c_int32)]
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        BP = ctypes.POINTER(Box)
+        sig = {
+            "orc_minimum_image": [BP, P, i64],
+            "orc_ball_count": [BP, P, i64, P, i64, f64, i32, P],
+            "orc_ball_fill": [BP, P, i64, P, i64, f64, i32, P, P, P],
+            "orc_rdf": [BP, P, i64, P, i64, i64, f64, f64, i32, f64, P, P, P],
+            "orc_knn": [BP, P, i64, P, i64, i32, i32, i32, f64, P, P, P],
+            "orc_pmft2d": [BP, P, i64, P, P, i64, i64, i64, f64, f64, f64, i32, f64, f64, P, P, P],
+            "orc_smooth_rdf": [BP, P, i64, i64, f64, f64, P],
+            "orc_smooth_rdf_row": [BP, P, i64, i64, P, i64, f64, f64, P],
+            "orc_smooth_rdf_grad": [BP, P, i64, i64, f64, f64, P, P, i64, P],
+            "orc_num_threads": [],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def make_box(L, tilt=(0.0, 0.0, 0.0), dim=3) -> Box:
+    L = list(L) if np.ndim(L) else [float(L)] * 3
+    b = Box()
+    for k in range(3):
+        b.L[k] = float(L[k])
+        b.tilt[k] = float(tilt[k])
+    b.dim = int(dim)
+    return b
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    assert a.ndim == 2 and a.shape[1] == 3
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def minimum_image(box: Box, d):
+    """Minimum image of FP64 displacements (General Utilities section)."""
+    d = np.ascontiguousarray(d, dtype=np.float64).copy()
+    lib().orc_minimum_image(ctypes.byref(box), _p(d), d.shape[0])
+    return d
+
+
+def ball_query(box: Box, points, r_max: float, query_points=None, exclude_ii=None,
+               rel_band: float = REL_BAND):
+    """All (i, j) with minimum-image distance below r_max (query API).
+
+    Returns CSR (offsets int64[nq+1], idx int32[P], r2 float64[P]) that also
+    holds the pairs in the band r_max^2 <= r^2 < r_max^2 (1 + rel_band), so a
+    caller can tell certain pairs from ambiguous ones.
+    """
+    pts = _f32(points)
+    if exclude_ii is None:
+        exclude_ii = query_points is None
+    q = pts if query_points is None else _f32(query_points)
+    r2lim = float(r_max) ** 2 * (1.0 + rel_band)
+    counts = np.zeros(q.shape[0], np.int64)
+    lib().orc_ball_count(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], r2lim,
+                         int(exclude_ii), _p(counts))
+    offsets = np.zeros(q.shape[0] + 1, np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    idx = np.empty(int(offsets[-1]), np.int32)
+    r2 = np.empty(int(offsets[-1]), np.float64)
+    lib().orc_ball_fill(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], r2lim,
+                        int(exclude_ii), _p(offsets), _p(idx), _p(r2))
+    return offsets, idx, r2
+
+
+def rdf_counts(box: Box, points, bins: int, r_max: float, r_min: float = 0.0,
+               query_points=None, exclude_ii=None, rel_band: float = REL_BAND):
+    """RDF pair histogram bounds (lo, hi, n_ambiguous); exact counts c obey lo <= c <= hi."""
+    pts = _f32(points)
+    if exclude_ii is None:
+        exclude_ii = query_points is None
+    q = pts if query_points is None else _f32(query_points)
+    lo = np.zeros(bins, np.uint64)
+    hi = np.zeros(bins, np.uint64)
+    amb = np.zeros(1, np.uint64)
+    lib().orc_rdf(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], bins,
+                  float(r_min), float(r_max), int(exclude_ii), rel_band, _p(lo), _p(hi), _p(amb))
+    return lo, hi, int(amb[0])
+
+
+def knn(box: Box, points, k: int, query_points=None, exclude_ii=None, extra: int = 1,
+        r_guard: float = 0.0):
+    """First k + extra neighbours per query in (r^2, j) order; idx -1 pads short rows."""
+    pts = _f32(points)
+    if exclude_ii is None:
+        exclude_ii = query_points is None
+    q = pts if query_points is None else _f32(query_points)
+    m = k + extra
+    idx = np.empty((q.shape[0], m), np.int32)
+    r2 = np.empty((q.shape[0], m), np.float64)
+    ln = np.empty(q.shape[0], np.int32)
+    lib().orc_knn(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], int(k), int(extra),
+                  int(exclude_ii), float(r_guard) ** 2 if r_guard > 0 else 0.0, _p(idx), _p(r2), _p(ln))
+    return idx, r2, ln
+
+
+def pmft2d_counts(box: Box, points, query_points, query_theta, nbx: int, nby: int,
+                  x_max: float, y_max: float, r_max: float, exclude_ii=None,
+                  rel_band: float = REL_BAND, abs_band=None):
+    """2D PMFT histogram bounds (lo, hi, n_ambiguous), counts[ix*nby + iy]."""
+    pts = _f32(points)
+    same = query_points is None
+    if exclude_ii is None:
+        exclude_ii = same
+    q = pts if same else _f32(query_points)
+    th = np.ascontiguousarray(query_theta, dtype=np.float32)
+    if abs_band is None:
+        abs_band = rel_band * max(x_max, y_max)
+    lo = np.zeros(nbx * nby, np.uint64)
+    hi = np.zeros(nbx * nby, np.uint64)
+    amb = np.zeros(1, np.uint64)
+    lib().orc_pmft2d(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), _p(th), q.shape[0], nbx, nby,
+                     float(x_max), float(y_max), float(r_max), int(exclude_ii), rel_band,
+                     float(abs_band), _p(lo), _p(hi), _p(amb))
+    return lo.reshape(nbx, nby), hi.reshape(nbx, nby), int(amb[0])
+
+
+def smooth_rdf_h(box: Box, points, bins: int, r_max: float, sigma: float):
+    """Smoothed RDF numerator h_b (FP64) over all ordered pairs."""
+    pts = _f32(points)
+    h = np.zeros(bins, np.float64)
+    lib().orc_smooth_rdf(ctypes.byref(box), _p(pts), pts.shape[0], bins, float(r_max),
+                         float(sigma), _p(h))
+    return h
+
+
+def smooth_rdf_row(box: Box, points, k: int, pk, bins: int, r_max: float, sigma: float):
+    """Contribution of both ordered pairs of particle k (placed at pk) to h."""
+    pts = _f32(points)
+    pk = np.ascontiguousarray(pk, dtype=np.float64)
+    h = np.zeros(bins, np.float64)
+    lib().orc_smooth_rdf_row(ctypes.byref(box), _p(pts), pts.shape[0], int(k), _p(pk), bins,
+                             float(r_max), float(sigma), _p(h))
+    return h
+
+
+def smooth_rdf_grad(box: Box, points, bins: int, r_max: float, sigma: float, grad_h, rows=None):
+    """dL/dp for the listed rows (all when rows is None), given dL/dh."""
+    pts = _f32(points)
+    gh = np.ascontiguousarray(grad_h, dtype=np.float64)
+    if rows is None:
+        out = np.zeros((pts.shape[0], 3), np.float64)
+        lib().orc_smooth_rdf_grad(ctypes.byref(box), _p(pts), pts.shape[0], bins, float(r_max),
+                                  float(sigma), _p(gh), None, 0, _p(out))
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros((rows.shape[0], 3), np.float64)
+        lib().orc_smooth_rdf_grad(ctypes.byref(box), _p(pts), pts.shape[0], bins, float(r_max),
+                                  float(sigma), _p(gh), _p(rows), rows.shape[0], _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Normalisation (closed forms, FP64).  The paper relates g(r) to the PMF by
+# g = exp(-beta F) (PMFT section) and computes the PMFT as minus the log of
+# the accumulated histogram; it states no normalisation, so these follow the
+# usual ideal-gas one.
+# ---------------------------------------------------------------------------
+
+def box_volume(L, dim=3):
+    L = np.broadcast_to(np.asarray(L, np.float64), (3,))
+    return float(L[0] * L[1] * (L[2] if dim == 3 else 1.0))
+
+
+def shell_volumes(bins: int, r_min: float, r_max: float, dim: int = 3):
+    e = r_min + np.arange(bins + 1, dtype=np.float64) * ((r_max - r_min) / bins)
+    if dim == 3:
+        return 4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)
+    return math.pi * (e[1:] ** 2 - e[:-1] ** 2)
+
+
+def rdf_normalize(counts, n_points, n_query, volume, r_min, r_max, dim=3, n_frames=1):
+    """g_b = h_b / (N_q * rho * dV_b), rho = N_p / V, summed frames in the denominator."""
+    counts = np.asarray(counts, np.float64)
+    dv = shell_volumes(counts.shape[-1], r_min, r_max, dim)
+    rho = n_points / volume
+    return counts / (n_frames * n_query * rho * dv)
+
+
+def pmf_from_rdf(g):
+    """beta F(r) = -ln g(r); +inf where g = 0 (PMFT section's PMF relation)."""
+    g = np.asarray(g, np.float64)
+    with np.errstate(divide="ignore"):
+        return -np.log(g)
+
+
+def pmft2d_from_counts(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
+    """beta F(x, y) = -ln(counts / (N_q * rho * dx * dy * frames)); +inf at 0."""
+    counts = np.asarray(counts, np.float64)
+    nbx, nby = counts.shape
+    dxdy = (2 * x_max / nbx) * (2 * y_max / nby)
+    pcf = counts / (n_frames * n_query * (n_points / area) * dxdy)
+    with np.errstate(divide="ignore"):
+        return -np.log(pcf)
+
+
+def smooth_rdf_g(h, n_points, volume, r_max):
+    """g_b = h_b / (N * rho * dV_b) on bins of [0, r_max)."""
+    return rdf_normalize(h, n_points, n_points, volume, 0.0, r_max, 3)
