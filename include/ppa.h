@@ -1,0 +1,153 @@
+/*
+ * ppa: periodic pair analysis on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libppa.so: neighbor queries in periodic triclinic boxes and the
+ * per-bond histograms built from them (RDF, 2D PMFT), after the neighbor
+ * machinery and analysis modules of the freud paper (arXiv:1906.06317,
+ * sections "Implementation" and "Features").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Box.  ppa_box holds the edge lengths L = (Lx, Ly, Lz), the tilt factors
+ *   (xy, xz, yz) and the dimension (2 or 3).  Its lattice vectors are
+ *   a1 = (Lx, 0, 0), a2 = (xy Ly, Ly, 0), a3 = (xz Lz, yz Lz, Lz), and the box
+ *   is centred on the origin.  The paper builds a box from three edge lengths
+ *   or a 3x3 matrix ("Implementation"); ppa_box_from_matrix accepts the
+ *   latter in upper-triangular form.  In 2D, Lz, xz, yz and z are ignored.
+ * Points.  Positions are N x 3 float32, row-major (x, y, z), the paper's
+ *   "N x 3 array".  Points may lie outside the box; they are folded in.
+ * Minimum image.  Every query needs r_max < min_k(d_k)/2, where d_k is the
+ *   perpendicular width of the box across face k.  Then the pair vector is
+ *   the unique periodic image shorter than r_max.
+ * Memory.  Every pointer argument named *_dev or documented as "device" is
+ *   device memory owned by the caller; the library allocates nothing on the
+ *   device.  The scratch space each call needs is the caller's workspace
+ *   `ws` of `ws_bytes` bytes (size from ppa_workspace_bytes, 256-byte
+ *   aligned).  Inputs must stay valid until the stream work is done.
+ * Streams.  All compute calls are asynchronous on the given hipStream_t and
+ *   return after enqueueing.  Errors found on the host are returned at
+ *   once; errors found on the device (non-finite input, output capacity)
+ *   are recorded in a status word inside `ws` and returned by
+ *   ppa_sync_status, which waits for the stream.
+ * Histograms are accumulated into (+=), as the paper's reset=False
+ *   accumulation over frames ("Implementation"); zero them to start over.
+ * Return value: PPA_OK or a negative PPA_E* code; ppa_last_error() gives a
+ *   message for the calling thread's last failure.
+ */
+#ifndef PPA_H
+#define PPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double L[3];    /* Lx, Ly, Lz (> 0, finite) */
+    double tilt[3]; /* xy, xz, yz (finite) */
+    int32_t dim;    /* 2 or 3 */
+} ppa_box;
+
+enum {
+    PPA_OK = 0,
+    PPA_EINVAL = -1,     /* null pointer, negative size, bad bins/k/flags, r_max <= r_min */
+    PPA_EBOX = -2,       /* non-finite or non-positive box, or matrix not upper triangular */
+    PPA_ERANGE = -3,     /* cutoff at or beyond half the smallest perpendicular width */
+    PPA_EWORKSPACE = -4, /* ws null, misaligned or smaller than ppa_workspace_bytes */
+    PPA_EDEVICE = -5,    /* a HIP call failed */
+    PPA_ECAPACITY = -6,  /* more pairs than the output capacity (device status) */
+    PPA_ENONFINITE = -7  /* a NaN or infinite coordinate (device status) */
+};
+
+/* Workspace flag: the call writes a NeighborList (adds room for the row
+ * counts and the scan of the row offsets). */
+#define PPA_WS_NLIST 1
+
+/* Box from a 3x3 matrix whose columns are the lattice vectors (row-major
+ * m[r*3+c]).  The matrix must be upper triangular with a positive diagonal;
+ * a general matrix must be rotated into that form by the caller. */
+int ppa_box_from_matrix(const double m[9], int32_t dim, ppa_box* out);
+
+/* Perpendicular widths d_k of the box (host only, no device work). */
+int ppa_box_widths(const ppa_box* box, double widths[3]);
+
+/* Workspace bytes for a query on n points (and nq separate query points,
+ * 0 when the points query themselves) with cutoff r_cut.  flags is
+ * PPA_WS_NLIST for calls that write a NeighborList, else 0.  Host only.
+ * Returns PPA_ERANGE for an over-long cutoff. */
+int ppa_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, float r_cut, int32_t flags,
+                        size_t* bytes);
+
+/* Ball query: the NeighborList of all (i, j) with |p_j - q_i| < r_max
+ * (minimum image), excluding i == j when exclude_ii is set (the paper's
+ * query API with an r_max query argument and exclude_ii, "Implementation"
+ * and the common-neighbor example; the NeighborList of "General
+ * Utilities").
+ *   pts [n x 3] device; qpts [nq x 3] device, or NULL to query pts with
+ *     themselves (then nq must equal n).
+ *   flags: reserved, must be 0.
+ *   offsets [nq + 1] int64 device: CSR row pointer, rows in query order
+ *     (the paper's promise of sorted query order); offsets[nq] = pairs.
+ *   counts [nq] int32 device or NULL: row lengths.
+ *   point_idx [capacity] int32 device: neighbour point index j per pair.
+ *   dist [capacity] float32 device or NULL: |p_j - q_i| per pair.
+ *   n_pairs_dev: int64 device, receives the pair count (also when it
+ *     exceeds capacity, in which case the status is PPA_ECAPACITY and
+ *     point_idx/dist hold an incomplete list).
+ * Within a row, pairs are in a fixed order for a given input (stencil cell
+ * by stencil cell, then by point index); the output is deterministic.
+ * Two passes: row lengths, a prefix scan into offsets, then the fill. */
+int ppa_query_ball(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   float r_max, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
+                   int64_t* offsets, int32_t* counts, int32_t* point_idx, float* dist,
+                   int64_t capacity, int64_t* n_pairs_dev, hipStream_t stream);
+
+/* RDF pair histogram: counts[b] += number of ball pairs with
+ * r_min + b dr <= r < r_min + (b+1) dr, dr = (r_max - r_min)/bins (the
+ * density module's RDF configured by bins, r_max, r_min, "Analysis
+ * Modules" and the LAMMPS example).  Pairs are the ball pairs of
+ * ppa_query_ball with cutoff r_max.  When offsets is non-NULL the same
+ * pass also writes the NeighborList exactly as ppa_query_ball does
+ * (neighbours found once, used twice: the paper's lazy iteration of pairs
+ * inside the analysis).  counts [bins] uint64 device, accumulated. */
+int ppa_rdf(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+            int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+            size_t ws_bytes, uint64_t* counts_hist, int64_t* offsets, int32_t* counts,
+            int32_t* point_idx, float* dist, int64_t capacity, int64_t* n_pairs_dev,
+            hipStream_t stream);
+
+/* RDF histogram from a stored NeighborList's distances (the paper's reuse of
+ * a NeighborList across analyses, "Implementation").  dist [*n_pairs_dev]
+ * float32 device, at most `capacity` are read; counts_hist accumulated. */
+int ppa_rdf_from_nlist(const float* dist, const int64_t* n_pairs_dev, int64_t capacity,
+                       int32_t bins, float r_min, float r_max, uint64_t* counts_hist,
+                       hipStream_t stream);
+
+/* Profiling hook: the next ppa_query_ball / ppa_rdf call made by this
+ * thread records, on its stream, count_start / count_stop around its
+ * row-count kernel and fill_start / fill_stop around its fill kernel (the
+ * kernel that writes the list and the histogram), then forgets them.  Any
+ * event may be NULL; the events belong to the caller.  Used to time single
+ * kernels inside a longer stream of work. */
+int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,
+                     hipEvent_t fill_stop);
+
+/* Waits for the stream and returns the device status of the last call that
+ * used this workspace (PPA_OK, PPA_ECAPACITY or PPA_ENONFINITE). */
+int ppa_sync_status(const void* ws, hipStream_t stream);
+
+/* Message describing the calling thread's last error. */
+const char* ppa_last_error(void);
+
+/* Library version string. */
+const char* ppa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPA_H */

@@ -1,0 +1,322 @@
+"""ppa: periodic pair analysis on AMD Instinct MI355X (gfx950).
+
+Thin Python binding of libppa.so (C ABI in include/ppa.h).  Every step of
+the computation runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch provides device memory and the current
+stream.  There is no CPU fallback: if the library cannot be loaded, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libppa.so")
+
+PPA_OK = 0
+PPA_EINVAL = -1
+PPA_EBOX = -2
+PPA_ERANGE = -3
+PPA_EWORKSPACE = -4
+PPA_EDEVICE = -5
+PPA_ECAPACITY = -6
+PPA_ENONFINITE = -7
+PPA_WS_NLIST = 1
+
+_ERRNAMES = {
+    PPA_EINVAL: "PPA_EINVAL", PPA_EBOX: "PPA_EBOX", PPA_ERANGE: "PPA_ERANGE",
+    PPA_EWORKSPACE: "PPA_EWORKSPACE", PPA_EDEVICE: "PPA_EDEVICE",
+    PPA_ECAPACITY: "PPA_ECAPACITY", PPA_ENONFINITE: "PPA_ENONFINITE",
+}
+
+
+class PPAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CBox(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("tilt", ctypes.c_double * 3), ("dim", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class Box:
+    """Periodic box: edge lengths L, tilts (xy, xz, yz), dimension 2 or 3."""
+    L: tuple
+    tilt: tuple = (0.0, 0.0, 0.0)
+    dim: int = 3
+
+    @staticmethod
+    def cube(L, dim=3):
+        return Box((float(L),) * 3 if dim == 3 else (float(L), float(L), 1.0), (0.0, 0.0, 0.0), dim)
+
+    @staticmethod
+    def from_matrix(m, dim=3):
+        """Box from a 3x3 upper-triangular matrix whose columns are the lattice vectors."""
+        m = np.ascontiguousarray(m, dtype=np.float64).reshape(9)
+        out = CBox()
+        _check(lib().ppa_box_from_matrix(m.ctypes.data_as(ctypes.c_void_p), dim, ctypes.byref(out)))
+        return Box(tuple(out.L), tuple(out.tilt), int(out.dim))
+
+    def c(self) -> CBox:
+        b = CBox()
+        for k in range(3):
+            b.L[k] = float(self.L[k])
+            b.tilt[k] = float(self.tilt[k])
+        b.dim = int(self.dim)
+        return b
+
+    @property
+    def volume(self) -> float:
+        return float(self.L[0] * self.L[1] * (self.L[2] if self.dim == 3 else 1.0))
+
+    def widths(self):
+        w = (ctypes.c_double * 3)()
+        _check(lib().ppa_box_widths(ctypes.byref(self.c()), w))
+        return tuple(w)
+
+
+_lib = None
+
+
+def lib():
+    """Loads libppa.so (building it first if it is missing)."""
+    global _lib
+    if _lib is None:
+        # torch first: its bundled HIP runtime then also serves libppa (same
+        # soname), so torch's streams and memory are valid in the library
+        import torch  # noqa: F401
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P, i32, i64, f32, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                ctypes.c_size_t)
+        BP = ctypes.POINTER(CBox)
+        sig = {
+            "ppa_box_from_matrix": [P, i32, BP],
+            "ppa_box_widths": [BP, P],
+            "ppa_workspace_bytes": [BP, i64, i64, f32, i32, ctypes.POINTER(sz)],
+            "ppa_query_ball": [BP, P, i64, P, i64, f32, i32, i32, P, sz, P, P, P, P, i64, P, P],
+            "ppa_rdf": [BP, P, i64, P, i64, i32, f32, f32, i32, i32, P, sz, P, P, P, P, P, i64, P, P],
+            "ppa_rdf_from_nlist": [P, P, i64, i32, f32, f32, P, P],
+            "ppa_sync_status": [P, P],
+            "ppa_profile_next": [P, P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.ppa_last_error.restype = ctypes.c_char_p
+        L.ppa_last_error.argtypes = []
+        L.ppa_version.restype = ctypes.c_char_p
+        L.ppa_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != PPA_OK:
+        raise PPAError(rc, lib().ppa_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _points(points):
+    torch = _torch()
+    if not isinstance(points, torch.Tensor):
+        points = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float32))
+    if points.device.type != "cuda":
+        points = points.to("cuda")
+    points = points.to(torch.float32).contiguous()
+    if points.ndim != 2 or points.shape[1] != 3:
+        raise ValueError("points must be an N x 3 array")
+    return points
+
+
+class Workspace:
+    """Caller-owned device scratch memory, grown on demand (256-byte aligned)."""
+
+    def __init__(self):
+        self.buf = None
+        self.ptr = 0
+        self.nbytes = 0
+
+    def get(self, nbytes):
+        torch = _torch()
+        if self.buf is None or self.nbytes < nbytes:
+            self.buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+            base = self.buf.data_ptr()
+            self.ptr = (base + 255) // 256 * 256
+            self.nbytes = int(nbytes)
+        return ctypes.c_void_p(self.ptr), ctypes.c_size_t(self.nbytes)
+
+    def status(self, stream=None):
+        return lib().ppa_sync_status(ctypes.c_void_p(self.ptr), _stream(stream))
+
+
+_default_ws = None
+
+
+def default_workspace():
+    global _default_ws
+    if _default_ws is None:
+        _default_ws = Workspace()
+    return _default_ws
+
+
+def workspace_bytes(box: Box, n, nq, r_cut, flags=0):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), float(r_cut),
+                                     int(flags), ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class NeighborList:
+    """Pairs found by a query, as CSR in query order: row q is
+    point_idx[offsets[q]:offsets[q + 1]] (and dist likewise)."""
+    offsets: "object"     # int64 [nq + 1]; offsets[nq] = n_pairs
+    counts: "object"      # int32 [nq]
+    point_idx: "object"   # int32 [n_pairs]
+    dist: "object"        # float32 [n_pairs] or None
+    n_pairs: int
+
+    def query_point_indices(self):
+        """Query index of every pair (length n_pairs), as in the paper's NeighborList."""
+        torch = _torch()
+        return torch.repeat_interleave(
+            torch.arange(self.counts.shape[0], device=self.counts.device, dtype=torch.int32),
+            self.counts.to(torch.int64))
+
+
+def _estimate_pairs(box: Box, n, nq, r):
+    rho = n / box.volume
+    vball = (4.0 / 3.0) * math.pi * r ** 3 if box.dim == 3 else math.pi * r * r
+    return int(nq * rho * vball * 1.25) + 4096
+
+
+def _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist, hist, bins,
+               r_min, want_nl, ws, stream, check):
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    ws = ws or default_workspace()
+    need = workspace_bytes(box, n, 0 if q is None else nq, r_max, PPA_WS_NLIST if want_nl else 0)
+    dev = pts.device
+    if nq == 0:
+        # nothing to query: an empty list and an unchanged histogram
+        if not want_nl:
+            return None
+        return NeighborList(torch.zeros(1, dtype=torch.int64, device=dev),
+                            torch.zeros(0, dtype=torch.int32, device=dev),
+                            torch.zeros(0, dtype=torch.int32, device=dev),
+                            torch.zeros(0, dtype=torch.float32, device=dev) if with_dist else None,
+                            0)
+    wptr, wlen = ws.get(need)
+    cb = box.c()
+    if not want_nl:
+        _check(lib().ppa_rdf(ctypes.byref(cb), _ptr(pts), n, _ptr(q), nq, int(bins), float(r_min),
+                             float(r_max), int(bool(exclude_ii)), 0, wptr, wlen, _ptr(hist),
+                             None, None, None, None, 0, None, _stream(stream)))
+        if check:
+            _check(ws.status(stream))
+        return None
+    if capacity is None:
+        capacity = _estimate_pairs(box, n, nq, r_max)
+    for attempt in range(2):
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+        counts = torch.empty(nq, dtype=torch.int32, device=dev)
+        pidx = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        dist = torch.empty(max(capacity, 1), dtype=torch.float32, device=dev) if with_dist else None
+        npairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        h0 = hist.clone() if (hist is not None and attempt == 0) else None
+        if hist is None:
+            rc = lib().ppa_query_ball(ctypes.byref(cb), _ptr(pts), n, _ptr(q), nq, float(r_max),
+                                      int(bool(exclude_ii)), 0, wptr, wlen, _ptr(offsets),
+                                      _ptr(counts), _ptr(pidx), _ptr(dist), int(capacity),
+                                      _ptr(npairs), _stream(stream))
+        else:
+            rc = lib().ppa_rdf(ctypes.byref(cb), _ptr(pts), n, _ptr(q), nq, int(bins),
+                               float(r_min), float(r_max), int(bool(exclude_ii)), 0, wptr, wlen,
+                               _ptr(hist), _ptr(offsets), _ptr(counts), _ptr(pidx), _ptr(dist),
+                               int(capacity), _ptr(npairs), _stream(stream))
+        _check(rc)
+        st = ws.status(stream)
+        if st == PPA_ECAPACITY and attempt == 0:
+            capacity = int(npairs.item())
+            if h0 is not None:
+                hist.copy_(h0)  # the histogram was complete; it is recomputed with the list
+            continue
+        if check or st == PPA_ENONFINITE:
+            _check(st)
+        break
+    np_ = int(npairs.item())
+    return NeighborList(offsets, counts, pidx[:np_], None if dist is None else dist[:np_], np_)
+
+
+def query_ball(box: Box, points, r_max, query_points=None, exclude_ii=None, capacity=None,
+               with_dist=True, ws=None, stream=None, check=True) -> NeighborList:
+    """All pairs (i, j) with |p_j - q_i| < r_max under periodic boundaries."""
+    return _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist, None, 0,
+                      0.0, True, ws, stream, check)
+
+
+def rdf_counts(box: Box, points, bins, r_max, r_min=0.0, query_points=None, exclude_ii=None,
+               counts=None, neighbor_list=False, capacity=None, ws=None, stream=None, check=True):
+    """RDF pair histogram (int64 [bins], accumulated into `counts` when given).
+
+    With neighbor_list=True the same pass also returns the NeighborList."""
+    torch = _torch()
+    if counts is None:
+        counts = torch.zeros(int(bins), dtype=torch.int64, device="cuda")
+    nl = _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, True, counts, bins,
+                    r_min, neighbor_list, ws, stream, check)
+    return (counts, nl) if neighbor_list else counts
+
+
+def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream=None):
+    torch = _torch()
+    if counts is None:
+        counts = torch.zeros(int(bins), dtype=torch.int64, device="cuda")
+    npairs = torch.tensor([nl.n_pairs], dtype=torch.int64, device=counts.device)
+    _check(lib().ppa_rdf_from_nlist(_ptr(nl.dist), _ptr(npairs), int(nl.n_pairs), int(bins),
+                                    float(r_min), float(r_max), _ptr(counts), _stream(stream)))
+    return counts
+
+
+def normalize_rdf(counts, n_points, n_query, volume, r_min, r_max, dim=3, n_frames=1):
+    """g_b = h_b / (N_q rho dV_b) with rho = N_p / V (float64, host)."""
+    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts, dtype=np.float64)
+    B = c.shape[-1]
+    e = r_min + np.arange(B + 1, dtype=np.float64) * ((r_max - r_min) / B)
+    dv = (4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)) if dim == 3 else math.pi * (e[1:] ** 2 - e[:-1] ** 2)
+    return c / (n_frames * n_query * (n_points / volume) * dv)
+
+
+def version():
+    return lib().ppa_version().decode()

@@ -1,0 +1,405 @@
+// C ABI of libppa: argument checks, box preparation in float64, workspace
+// layout and the sequence of kernel launches for each entry point.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace ppa {
+
+static thread_local char g_err[512] = "";
+struct ProfileEvents {
+    hipEvent_t ev[4];
+};
+static thread_local ProfileEvents g_prof = {{nullptr, nullptr, nullptr, nullptr}};
+
+// One-shot profiling events: before/after the count pass, before/after the
+// fill pass of the next query call.
+static ProfileEvents take_profile_events()
+{
+    ProfileEvents p = g_prof;
+    g_prof = ProfileEvents{{nullptr, nullptr, nullptr, nullptr}};
+    return p;
+}
+
+static void record(hipEvent_t e, hipStream_t s)
+{
+    if (e) (void)hipEventRecord(e, s);
+}
+
+int set_error(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_check(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return PPA_OK;
+    return set_error(PPA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Box matrix M with columns a1 = (Lx,0,0), a2 = (xy Ly, Ly, 0),
+// a3 = (xz Lz, yz Lz, Lz); its inverse; and the perpendicular widths
+// d_k = 1 / |row k of M^-1| (the distance between opposite faces).
+int prepare_box(const ppa_box* box, BoxPrep* out)
+{
+    if (!box) return set_error(PPA_EINVAL, "box is NULL");
+    if (box->dim != 2 && box->dim != 3) return set_error(PPA_EINVAL, "dim must be 2 or 3");
+    const int dim = box->dim;
+    for (int k = 0; k < dim; ++k)
+        if (!(isfinite(box->L[k]) && box->L[k] > 0.0))
+            return set_error(PPA_EBOX, "box length L[%d] must be finite and positive", k);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(box->tilt[k])) return set_error(PPA_EBOX, "tilt[%d] is not finite", k);
+    const double Lx = box->L[0], Ly = box->L[1], Lz = dim == 3 ? box->L[2] : 1.0;
+    const double xy = box->tilt[0], xz = dim == 3 ? box->tilt[1] : 0.0,
+                 yz = dim == 3 ? box->tilt[2] : 0.0;
+    double(*M)[3] = out->M;
+    double(*I)[3] = out->Minv;
+    memset(out, 0, sizeof(*out));
+    M[0][0] = Lx; M[0][1] = xy * Ly; M[0][2] = xz * Lz;
+    M[1][1] = Ly; M[1][2] = yz * Lz;
+    M[2][2] = Lz;
+    I[0][0] = 1.0 / Lx; I[0][1] = -xy / Lx; I[0][2] = (xy * yz - xz) / Lx;
+    I[1][1] = 1.0 / Ly; I[1][2] = -yz / Ly;
+    I[2][2] = 1.0 / Lz;
+    for (int k = 0; k < 3; ++k) {
+        const double r = sqrt(I[k][0] * I[k][0] + I[k][1] * I[k][1] + I[k][2] * I[k][2]);
+        out->width[k] = 1.0 / r;
+    }
+    if (dim == 2) out->width[2] = INFINITY;
+    out->dim = dim;
+    return PPA_OK;
+}
+
+// Cells of width >= r_cut (1 + 1e-5) per axis, so a pair closer than r_cut is
+// always in the 27-cell (9-cell) stencil even when rounding puts a point on
+// the wrong side of a cell face.  The count is capped near the number of
+// points: larger cells are always valid, only slower.
+int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g)
+{
+    const int dim = b.dim;
+    double nk[3] = {1, 1, 1};
+    for (int k = 0; k < dim; ++k) {
+        double v = floor(b.width[k] / (r_cut * (1.0 + 1e-5)));
+        nk[k] = v < 1.0 ? 1.0 : v;
+    }
+    const double cap = fmax(64.0, 2.0 * (double)n_hint);
+    double total = nk[0] * nk[1] * nk[2];
+    if (total > cap) {
+        const double f = pow(cap / total, 1.0 / dim);
+        for (int k = 0; k < dim; ++k) nk[k] = fmax(1.0, floor(nk[k] * f));
+    }
+    for (int k = 0; k < 3; ++k) g->n[k] = (int)nk[k];
+    g->ncells = g->n[0] * g->n[1] * g->n[2];
+    g->nsten = dim == 3 ? 27 : 9;
+    for (int s = 0; s < 27; ++s) {
+        double d[3] = {(double)(s % 3 - 1), (double)((s / 3) % 3 - 1), dim == 3 ? (double)(s / 9 - 1) : 0.0};
+        if (s >= g->nsten) d[0] = d[1] = d[2] = 0.0;
+        double f[3] = {d[0] / g->n[0], d[1] / g->n[1], d[2] / g->n[2]};
+        g->off[s][0] = (float)(b.M[0][0] * f[0] + b.M[0][1] * f[1] + b.M[0][2] * f[2]);
+        g->off[s][1] = (float)(b.M[1][1] * f[1] + b.M[1][2] * f[2]);
+        g->off[s][2] = dim == 3 ? (float)(b.M[2][2] * f[2]) : 0.f;
+    }
+    return PPA_OK;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static void carve_cells(char* base, size_t& off, const Grid& g, int64_t n, CellList* cl)
+{
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    cl->n = n;
+    cl->cell_of = (int*)take(sizeof(int) * (size_t)n);
+    cl->local = (float4*)take(sizeof(float4) * (size_t)n);
+    cl->sorted = (float4*)take(sizeof(float4) * (size_t)n);
+    cl->cell_count = (int*)take(sizeof(int) * (size_t)g.ncells);
+    cl->cell_start = (int*)take(sizeof(int) * ((size_t)g.ncells + 1));
+    cl->cursor = (int*)take(sizeof(int) * (size_t)g.ncells);
+    const size_t nf = scan_flag_count(g.ncells);
+    cl->scan_flags = (unsigned long long*)take(sizeof(unsigned long long) * nf + 256);
+    cl->scan_ticket = cl->scan_flags ? (int*)(cl->scan_flags + nf) : nullptr;
+}
+
+// Workspace: 256-byte header (status word, counters), the points' cell list,
+// the query points' cell list when they differ, and for query-ordered rows a
+// row-count array plus the scan state for the row offsets.
+size_t workspace_layout(const Grid& g, int64_t n, int64_t nq, int32_t flags, void* base_v,
+                        Workspace* ws)
+{
+    char* base = (char*)base_v;
+    size_t off = 0;
+    ws->status = base ? (unsigned*)base : nullptr;
+    ws->counters = base ? (unsigned long long*)(base + 64) : nullptr;
+    off = 256;
+    carve_cells(base, off, g, n, &ws->pts);
+    if (nq > 0) {
+        carve_cells(base, off, g, nq, &ws->qry);
+    } else {
+        ws->qry = ws->pts;
+    }
+    ws->row_scan_flags = nullptr;
+    ws->row_scan_ticket = nullptr;
+    ws->qry_row_counts = nullptr;
+    const int64_t nrow = nq > 0 ? nq : n;
+    if (flags & PPA_WS_NLIST) {  // row counts and the scan state of the row offsets
+        const size_t nf = scan_flag_count(nrow);
+        void* rc = base ? base + off : nullptr;
+        off = align_up(off + sizeof(int) * (size_t)nrow);
+        ws->row_scan_flags = base ? (unsigned long long*)(base + off) : nullptr;
+        ws->row_scan_ticket = base ? (int*)(ws->row_scan_flags + nf) : nullptr;
+        off = align_up(off + sizeof(unsigned long long) * nf + 256);
+        ws->qry_row_counts = (int*)rc;
+    }
+    ws->bytes = off;
+    return off;
+}
+
+}  // namespace ppa
+
+using namespace ppa;
+
+namespace {
+
+struct QueryCall {
+    const ppa_box* box;
+    const float* pts;
+    int64_t n;
+    const float* qpts;
+    int64_t nq;
+    float r_max;
+    int32_t exclude_ii;
+    int32_t flags;
+    void* ws;
+    size_t ws_bytes;
+    bool want_nl;
+    int64_t* offsets;
+    int32_t* counts;
+    int32_t* point_idx;
+    float* dist;
+    int64_t capacity;
+    int64_t* n_pairs_dev;
+    bool want_hist;
+    int32_t bins;
+    float r_min;
+    uint64_t* hist;
+    hipStream_t stream;
+};
+
+int check_cutoff(const BoxPrep& bp, double r)
+{
+    const double half = 0.5 * fmin(bp.width[0], fmin(bp.width[1], bp.width[2]));
+    if (!(r < half))
+        return set_error(PPA_ERANGE,
+                         "cutoff %.9g must be below half the smallest perpendicular box width "
+                         "(%.9g)",
+                         r, half);
+    return PPA_OK;
+}
+
+int run_pairs(const QueryCall& c)
+{
+    if (!c.pts && c.n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (c.n < 0 || c.nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (c.n > 0x7fffffffLL || c.nq > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "point counts are limited to 2^31 - 1");
+    if (!c.qpts && c.nq != c.n)
+        return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (!(isfinite(c.r_max) && c.r_max > 0.f))
+        return set_error(PPA_EINVAL, "r_max must be finite and positive");
+    if (c.flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", c.flags);
+    if (c.want_nl) {
+        if (!c.offsets || !c.n_pairs_dev || (!c.point_idx && c.capacity > 0))
+            return set_error(PPA_EINVAL, "offsets, point_idx and n_pairs_dev are required");
+        if (c.capacity < 0) return set_error(PPA_EINVAL, "capacity must be >= 0");
+    }
+    if (c.want_hist) {
+        if (!c.hist) return set_error(PPA_EINVAL, "histogram pointer is NULL");
+        if (c.bins < 1) return set_error(PPA_EINVAL, "bins must be >= 1");
+        if (!(isfinite(c.r_min) && c.r_min >= 0.f && c.r_min < c.r_max))
+            return set_error(PPA_EINVAL, "need 0 <= r_min < r_max");
+    }
+    BoxPrep bp;
+    int rc = prepare_box(c.box, &bp);
+    if (rc) return rc;
+    if ((rc = check_cutoff(bp, c.r_max))) return rc;
+    Grid g;
+    make_grid(bp, c.r_max, c.n, &g);
+    Workspace W{};
+    const int64_t nq_sep = c.qpts ? c.nq : 0;
+    const int32_t lay_flags = c.want_nl ? PPA_WS_NLIST : 0;
+    const size_t need = workspace_layout(g, c.n, nq_sep, lay_flags, nullptr, &W);
+    if (!c.ws || ((uintptr_t)c.ws & 255) || c.ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, c.ws_bytes);
+    workspace_layout(g, c.n, nq_sep, lay_flags, c.ws, &W);
+    hipStream_t s = c.stream;
+
+    // n_pairs_dev doubles as the reservation counter of the one-pass mode
+    launch_zero(W, g, c.qpts != nullptr, nullptr, 0, s);
+    launch_build_cells(c.pts, W.pts, bp, g, W.status, s);
+    if (c.qpts) launch_build_cells(c.qpts, W.qry, bp, g, W.status, s);
+
+    PairArgs A{};
+    A.cand = W.pts.sorted;
+    A.cand_start = W.pts.cell_start;
+    A.qsorted = W.qry.sorted;
+    A.q_start = W.qry.cell_start;
+    for (int k = 0; k < 3; ++k) A.geom.n[k] = g.n[k];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    A.geom.center = g.nsten / 2;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    A.geom.r2max = c.r_max * c.r_max;
+    A.offsets = c.offsets;
+    A.point_idx = c.point_idx;
+    A.dist = c.dist;
+    A.capacity = c.capacity;
+    A.status = W.status;
+    A.hist = (unsigned long long*)c.hist;
+    A.bins = c.want_hist ? c.bins : 0;
+    A.r_min = c.r_min;
+    A.inv_dr = c.want_hist ? (float)((double)c.bins / ((double)c.r_max - (double)c.r_min)) : 0.f;
+    const int blocks = pair_grid_blocks(g.ncells);
+    const int dim = bp.dim;
+    const int excl = !c.exclude_ii ? 0 : (c.qpts ? 2 : 1);
+
+    ProfileEvents pe = take_profile_events();
+    if (c.want_nl) {
+        A.counts = c.counts ? c.counts : W.qry_row_counts;
+        record(pe.ev[0], s);
+        launch_count(A, dim, excl, blocks, s);
+        record(pe.ev[1], s);
+        launch_scan_i64_total(A.counts, c.offsets, c.nq, W.row_scan_flags, W.row_scan_ticket,
+                              (unsigned long long*)c.n_pairs_dev, s);
+    }
+    record(pe.ev[2], s);
+    launch_fill(A, dim, excl, c.want_nl, c.want_hist, blocks, s);
+    record(pe.ev[3], s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppa_box_from_matrix(const double m[9], int32_t dim, ppa_box* out)
+{
+    if (!m || !out) return set_error(PPA_EINVAL, "NULL argument");
+    if (dim != 2 && dim != 3) return set_error(PPA_EINVAL, "dim must be 2 or 3");
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(m[i])) return set_error(PPA_EBOX, "matrix has a non-finite entry");
+    if (m[3] != 0.0 || m[6] != 0.0 || m[7] != 0.0)
+        return set_error(PPA_EBOX, "matrix must be upper triangular (rotate it first)");
+    const double Lx = m[0], Ly = m[4], Lz = dim == 3 ? m[8] : 1.0;
+    if (!(Lx > 0 && Ly > 0 && Lz > 0)) return set_error(PPA_EBOX, "diagonal must be positive");
+    out->L[0] = Lx;
+    out->L[1] = Ly;
+    out->L[2] = dim == 3 ? Lz : 1.0;
+    out->tilt[0] = m[1] / Ly;
+    out->tilt[1] = dim == 3 ? m[2] / Lz : 0.0;
+    out->tilt[2] = dim == 3 ? m[5] / Lz : 0.0;
+    out->dim = dim;
+    return PPA_OK;
+}
+
+int ppa_box_widths(const ppa_box* box, double widths[3])
+{
+    if (!widths) return set_error(PPA_EINVAL, "widths is NULL");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    for (int k = 0; k < 3; ++k) widths[k] = bp.width[k];
+    return PPA_OK;
+}
+
+int ppa_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, float r_cut, int32_t flags,
+                        size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (!(isfinite(r_cut) && r_cut > 0.f)) return set_error(PPA_EINVAL, "r_cut must be positive");
+    if (flags & ~PPA_WS_NLIST) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    if ((rc = check_cutoff(bp, r_cut))) return rc;
+    Grid g;
+    make_grid(bp, r_cut, n, &g);
+    Workspace W{};
+    *bytes = workspace_layout(g, n, nq, flags, nullptr, &W);
+    return PPA_OK;
+}
+
+int ppa_query_ball(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   float r_max, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
+                   int64_t* offsets, int32_t* counts, int32_t* point_idx, float* dist,
+                   int64_t capacity, int64_t* n_pairs_dev, hipStream_t stream)
+{
+    QueryCall c{box, pts, n, qpts, nq, r_max, exclude_ii, flags, ws, ws_bytes, true, offsets,
+                counts, point_idx, dist, capacity, n_pairs_dev, false, 0, 0.f, nullptr, stream};
+    return run_pairs(c);
+}
+
+int ppa_rdf(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+            int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+            size_t ws_bytes, uint64_t* counts_hist, int64_t* offsets, int32_t* counts,
+            int32_t* point_idx, float* dist, int64_t capacity, int64_t* n_pairs_dev,
+            hipStream_t stream)
+{
+    QueryCall c{box,     pts,    n,        qpts,      nq,       r_max,       exclude_ii, flags,
+                ws,      ws_bytes, offsets != nullptr, offsets, counts, point_idx, dist,
+                capacity, n_pairs_dev, true, bins, r_min, counts_hist, stream};
+    return run_pairs(c);
+}
+
+int ppa_rdf_from_nlist(const float* dist, const int64_t* n_pairs_dev, int64_t capacity,
+                       int32_t bins, float r_min, float r_max, uint64_t* counts_hist,
+                       hipStream_t stream)
+{
+    if (!n_pairs_dev || !counts_hist || (!dist && capacity > 0))
+        return set_error(PPA_EINVAL, "NULL argument");
+    if (bins < 1) return set_error(PPA_EINVAL, "bins must be >= 1");
+    if (!(isfinite(r_min) && isfinite(r_max) && r_min >= 0.f && r_min < r_max))
+        return set_error(PPA_EINVAL, "need 0 <= r_min < r_max");
+    const float inv_dr = (float)((double)bins / ((double)r_max - (double)r_min));
+    launch_hist_from_dist(dist, n_pairs_dev, capacity, bins, r_min, inv_dr,
+                          (unsigned long long*)counts_hist, stream);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+int ppa_sync_status(const void* ws, hipStream_t stream)
+{
+    if (!ws) return set_error(PPA_EINVAL, "workspace is NULL");
+    int rc = hip_check(hipStreamSynchronize(stream), "stream synchronize");
+    if (rc) return rc;
+    unsigned st = 0;
+    rc = hip_check(hipMemcpy(&st, ws, sizeof(st), hipMemcpyDeviceToHost), "read status");
+    if (rc) return rc;
+    if (st & kStatusNonFinite) return set_error(PPA_ENONFINITE, "input has a non-finite coordinate");
+    if (st & kStatusCapacity) return set_error(PPA_ECAPACITY, "more pairs than the output capacity");
+    return PPA_OK;
+}
+
+int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,
+                     hipEvent_t fill_stop)
+{
+    g_prof = ProfileEvents{{count_start, count_stop, fill_start, fill_stop}};
+    return PPA_OK;
+}
+
+const char* ppa_last_error(void) { return g_err; }
+
+const char* ppa_version(void) { return "ppa 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Cell-list build on the GPU: cell index, counting sort by cell, prefix scan.
+//
+// The paper's LinkCell finds neighbours with linked cell lists ("General
+// Utilities").  Here the list is rebuilt as flat arrays suited to a GPU:
+// every point gets a cell of a uniform grid in fractional coordinates, the
+// points are counting-sorted by cell (counts by atomics, an exclusive
+// decoupled look-back scan gives the cell starts, a scatter places them) and
+// each cell's run is then ordered by point index so the layout does not
+// depend on atomic arrival order.  Each point is stored relative to the
+// centre of its cell, so a pair vector later is a small difference plus a
+// per-stencil offset computed once in float64.
+#include "internal.hpp"
+
+namespace ppa {
+
+namespace {
+
+struct ZeroRanges {
+    unsigned* ptr[8];
+    long long words[8];
+    int count;
+};
+
+__global__ void zero_kernel(ZeroRanges z)
+{
+    for (int r = 0; r < z.count; ++r) {
+        unsigned* p = z.ptr[r];
+        const long long nw = z.words[r];
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+             i += (long long)gridDim.x * blockDim.x)
+            p[i] = 0u;
+    }
+}
+
+// Cell index and cell-centred local coordinates, in float64.
+__global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ pts, int64_t n,
+                                                     AssignBox B, int* __restrict__ cell_of,
+                                                     float4* __restrict__ local,
+                                                     int* __restrict__ cell_count,
+                                                     unsigned* __restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double p0 = (double)pts[3 * i];
+    double p1 = (double)pts[3 * i + 1];
+    double p2 = B.dim == 3 ? (double)pts[3 * i + 2] : 0.0;
+    if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) {
+        atomicOr(status, kStatusNonFinite);
+        p0 = p1 = p2 = 0.0;
+    }
+    // fractional coordinates s = M^-1 p, shifted to u = s + 1/2 and folded into [0, 1)
+    double u[3];
+    u[2] = B.dim == 3 ? B.Minv[2][2] * p2 + 0.5 : 0.5;
+    u[1] = B.Minv[1][1] * p1 + B.Minv[1][2] * p2 + 0.5;
+    u[0] = B.Minv[0][0] * p0 + B.Minv[0][1] * p1 + B.Minv[0][2] * p2 + 0.5;
+    int c[3];
+    double f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u[k] -= floor(u[k]);
+        int ck = (int)(u[k] * B.n[k]);
+        ck = ck < 0 ? 0 : (ck >= B.ni[k] ? B.ni[k] - 1 : ck);
+        c[k] = ck;
+        f[k] = u[k] - ((double)ck + 0.5) * B.inv_n[k];
+    }
+    if (B.dim != 3) f[2] = 0.0;
+    const double x = B.M[0][0] * f[0] + B.M[0][1] * f[1] + B.M[0][2] * f[2];
+    const double y = B.M[1][1] * f[1] + B.M[1][2] * f[2];
+    const double z = B.M[2][2] * f[2];
+    const int cell = (c[2] * B.ni[1] + c[1]) * B.ni[0] + c[0];
+    cell_of[i] = cell;
+    local[i] = make_float4((float)x, (float)y, (float)z, __int_as_float((int)i));
+    atomicAdd(&cell_count[cell], 1);
+}
+
+__global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int* __restrict__ cell_of,
+                                                      const float4* __restrict__ local,
+                                                      const int* __restrict__ cell_start,
+                                                      int* __restrict__ cursor,
+                                                      float4* __restrict__ sorted)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_of[i];
+    const int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
+    sorted[pos] = local[i];
+}
+
+// Order each cell's run by point index (insertion sort, one thread per cell).
+__global__ void __launch_bounds__(256) order_cells_kernel(int ncells,
+                                                          const int* __restrict__ cell_start,
+                                                          float4* __restrict__ sorted)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int b = cell_start[c], e = cell_start[c + 1];
+    for (int i = b + 1; i < e; ++i) {
+        const float4 v = sorted[i];
+        const int key = __float_as_int(v.w);
+        int j = i - 1;
+        while (j >= b && __float_as_int(sorted[j].w) > key) {
+            sorted[j + 1] = sorted[j];
+            --j;
+        }
+        sorted[j + 1] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix scan, single pass with decoupled look-back.  Tiles take
+// ids from a ticket counter in launch order, so a tile only ever waits on
+// tiles that are already running or finished.  Each tile publishes its
+// aggregate, then walks back over predecessors until it meets an inclusive
+// prefix.  A status word packs the state in its top two bits (1 aggregate,
+// 2 inclusive prefix) and the value in the low 62.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = kScanTile / kScanThreads;
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagInc = 2ull << 62;
+constexpr unsigned long long kValueMask = (1ull << 62) - 1;
+
+template <typename Out>
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restrict__ in,
+                                                            Out* __restrict__ out, int64_t n,
+                                                            unsigned long long* flags,
+                                                            int* ticket,
+                                                            unsigned long long* total_out)
+{
+    __shared__ long long s_warp[kScanThreads / kWave];
+    __shared__ long long s_prefix;
+    __shared__ int s_tile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long v[kScanItems];
+    long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < n ? (long long)in[i] : 0;
+        sum += v[k];
+    }
+    // block-wide exclusive scan of per-thread sums
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    long long incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        long long t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    if (lane == kWave - 1) s_warp[wv] = incl;
+    __syncthreads();
+    long long warp_before = 0, block_total = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < wv) warp_before += s_warp[w];
+        block_total += s_warp[w];
+    }
+    if (threadIdx.x == 0) {
+        long long prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&flags[0], kFlagInc | (unsigned long long)block_total,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&flags[tile], kFlagAgg | (unsigned long long)block_total,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = tile - 1;
+            while (true) {
+                unsigned long long f;
+                do {
+                    f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                } while ((f >> 62) == 0);
+                prefix += (long long)(f & kValueMask);
+                if ((f >> 62) == 2) break;
+                --j;
+            }
+            __hip_atomic_store(&flags[tile],
+                               kFlagInc | (unsigned long long)(prefix + block_total),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_prefix = prefix;
+        const int64_t ntiles = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
+        if (tile == ntiles - 1) {
+            out[n] = (Out)(prefix + block_total);
+            if (total_out) *total_out = (unsigned long long)(prefix + block_total);
+        }
+    }
+    __syncthreads();
+    long long run = s_prefix + warp_before + (incl - sum);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < n) out[i] = (Out)run;
+        run += v[k];
+    }
+}
+
+}  // namespace
+
+size_t scan_flag_count(int64_t n)
+{
+    int64_t t = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(t < 1 ? 1 : t);
+}
+
+template <typename Out>
+static void launch_scan(const int* in, Out* out, int64_t n, unsigned long long* flags, int* ticket,
+                        unsigned long long* total, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)scan_flag_count(n);
+    hipLaunchKernelGGL(scan_kernel<Out>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out,
+                       n, flags, ticket, total);
+}
+
+void launch_scan_i64(const int* in, int64_t* out, int64_t n, unsigned long long* flags, int* ticket,
+                     hipStream_t s)
+{
+    launch_scan<int64_t>(in, out, n, flags, ticket, nullptr, s);
+}
+
+void launch_scan_i64_total(const int* in, int64_t* out, int64_t n, unsigned long long* flags,
+                           int* ticket, unsigned long long* total, hipStream_t s)
+{
+    launch_scan<int64_t>(in, out, n, flags, ticket, total, s);
+}
+
+void launch_zero(Workspace& ws, const Grid& g, bool separate_queries, void* extra,
+                 size_t extra_bytes, hipStream_t s)
+{
+    ZeroRanges z{};
+    auto add = [&](void* p, size_t bytes) {
+        z.ptr[z.count] = (unsigned*)p;
+        z.words[z.count] = (long long)((bytes + 3) / 4);
+        ++z.count;
+    };
+    add(ws.status, 256);  // status word and counters share the header
+    const size_t nf = scan_flag_count(g.ncells);
+    add(ws.pts.cell_count, sizeof(int) * (size_t)g.ncells);
+    add(ws.pts.cursor, sizeof(int) * (size_t)g.ncells);
+    add(ws.pts.scan_flags, sizeof(unsigned long long) * nf + 256);
+    if (separate_queries) {
+        add(ws.qry.cell_count, sizeof(int) * (size_t)g.ncells);
+        add(ws.qry.cursor, sizeof(int) * (size_t)g.ncells);
+        add(ws.qry.scan_flags, sizeof(unsigned long long) * nf + 256);
+    }
+    if (ws.row_scan_flags)
+        add(ws.row_scan_flags, sizeof(unsigned long long) * scan_flag_count(ws.qry.n) + 256);
+    if (extra) add(extra, extra_bytes);
+    hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, s, z);
+}
+
+void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const Grid& g,
+                        unsigned* status, hipStream_t s)
+{
+    AssignBox ab;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            ab.M[r][c] = b.M[r][c];
+            ab.Minv[r][c] = b.Minv[r][c];
+        }
+    for (int k = 0; k < 3; ++k) {
+        ab.n[k] = (double)g.n[k];
+        ab.inv_n[k] = 1.0 / (double)g.n[k];
+        ab.ni[k] = g.n[k];
+    }
+    ab.dim = b.dim;
+    const int64_t n = cl.n;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (n > 0)
+        hipLaunchKernelGGL(assign_kernel, dim3(blocks), dim3(256), 0, s, pts, n, ab, cl.cell_of,
+                           cl.local, cl.cell_count, status);
+    launch_scan<int>(cl.cell_count, cl.cell_start, g.ncells, cl.scan_flags, cl.scan_ticket,
+                     nullptr, s);
+    if (n > 0) {
+        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.local,
+                           cl.cell_start, cl.cursor, cl.sorted);
+        hipLaunchKernelGGL(order_cells_kernel, dim3((g.ncells + 255) / 256), dim3(256), 0, s,
+                           g.ncells, cl.cell_start, cl.sorted);
+    }
+}
+
+}  // namespace ppa

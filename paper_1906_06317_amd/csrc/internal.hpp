@@ -1,0 +1,131 @@
+// Internal declarations shared by the host code and the HIP kernels of libppa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ppa.h"
+
+namespace ppa {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;             // threads per workgroup for the pair kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxSlots = 16;           // candidate slots a wave keeps in registers
+constexpr int kCandCap = kMaxSlots * kWave;
+constexpr int kScanTile = 2048;         // elements per workgroup in the prefix scans
+constexpr int kMaxLdsBins = 4096;       // histograms up to this size live in LDS
+
+// Device status bits (the status word in the workspace).
+constexpr unsigned kStatusNonFinite = 1u;
+constexpr unsigned kStatusCapacity = 2u;
+
+// Box prepared on the host in float64.
+struct BoxPrep {
+    double M[3][3];     // columns are the lattice vectors a1, a2, a3 (upper triangular)
+    double Minv[3][3];  // inverse (upper triangular)
+    double width[3];    // perpendicular widths d_k
+    int dim;
+};
+
+// Uniform cell grid in fractional coordinates: cell c covers
+// u in [c/n, (c+1)/n) per axis with u = s + 1/2 the fractional coordinate.
+struct Grid {
+    int n[3];
+    int ncells;
+    int nsten;          // 27 in 3D, 9 in 2D
+    float off[27][3];   // M (delta / n) for each stencil offset, delta = (dx, dy, dz)
+};
+
+// Kernel view of the box for the cell assignment (float64).
+struct AssignBox {
+    double M[3][3];
+    double Minv[3][3];
+    double n[3];
+    double inv_n[3];
+    int ni[3];
+    int dim;
+};
+
+// One cell list (points or query points) inside the workspace.
+struct CellList {
+    int* cell_of;        // [n]
+    float4* local;       // [n] position relative to its cell centre, w = index bits
+    float4* sorted;      // [n] `local` sorted by cell, then by index
+    int* cell_count;     // [ncells]  (zeroed, then counts)
+    int* cell_start;     // [ncells + 1]
+    int* cursor;         // [ncells]
+    unsigned long long* scan_flags;  // decoupled look-back state
+    int* scan_ticket;
+    int64_t n;
+};
+
+struct Workspace {
+    unsigned* status;             // device status bits
+    unsigned long long* counters; // [8] general counters (ticket, done)
+    CellList pts;
+    CellList qry;                 // == pts for self queries
+    // canonical-row mode: int64 exclusive scan of row counts
+    unsigned long long* row_scan_flags;
+    int* row_scan_ticket;
+    int* qry_row_counts;          // row counts when the caller passes none
+    size_t bytes;
+};
+
+// Host helpers (host.cpp).
+int prepare_box(const ppa_box* box, BoxPrep* out);
+int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g);
+size_t workspace_layout(const Grid& g, int64_t n, int64_t nq, int32_t flags, void* base,
+                        Workspace* ws);
+int set_error(int code, const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+
+// Launchers (cells.hip).
+void launch_zero(Workspace& ws, const Grid& g, bool separate_queries, void* extra,
+                 size_t extra_bytes, hipStream_t s);
+void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const Grid& g,
+                        unsigned* status, hipStream_t s);
+void launch_scan_i64(const int* in, int64_t* out, int64_t n, unsigned long long* flags,
+                     int* ticket, hipStream_t s);
+void launch_scan_i64_total(const int* in, int64_t* out, int64_t n, unsigned long long* flags,
+                           int* ticket, unsigned long long* total, hipStream_t s);
+size_t scan_flag_count(int64_t n);
+
+// Geometry of a pair query (pairs.hip).
+struct PairGeom {
+    int n[3];
+    int ncells;
+    int nsten;
+    int center;          // stencil slot of the home cell itself
+    float off[27][3];    // stencil offsets M (delta / n)
+    float r2max;
+};
+
+struct PairArgs {
+    const float4* cand;      // points sorted by cell
+    const int* cand_start;   // [ncells + 1]
+    const float4* qsorted;   // query points sorted by cell
+    const int* q_start;      // [ncells + 1]
+    PairGeom geom;
+    int32_t* counts;         // row lengths (count pass)
+    const int64_t* offsets;  // CSR row pointer (fill pass)
+    int32_t* point_idx;
+    float* dist;
+    int64_t capacity;
+    unsigned* status;
+    unsigned long long* hist;
+    int bins;
+    float r_min;
+    float inv_dr;
+};
+
+// excl: 0 keep i == j, 1 points query themselves (drop the query's own
+// entry), 2 separate query points (drop j == i by index).
+void launch_count(const PairArgs& a, int dim, int excl, int blocks, hipStream_t s);
+void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, int blocks,
+                 hipStream_t s);
+int pair_grid_blocks(int ncells);
+void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,
+                           float r_min, float inv_dr, unsigned long long* hist, hipStream_t s);
+
+}  // namespace ppa

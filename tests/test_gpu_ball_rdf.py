@@ -1,0 +1,239 @@
+"""GPU parity: ball query (NeighborList) and RDF against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_06317_amd import workloads
+from tests import brute
+from tests.parity import REL, check_hist, check_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ppa():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    import paper_1906_06317_amd as m
+    m.lib()
+    return m
+
+
+def _box(s):
+    import paper_1906_06317_amd as m
+    return m.Box(s.L, s.tilt, s.dim)
+
+
+def _oracle_rows(s, r_max, rows, query_points=None, exclude_ii=None):
+    ob = oracle.make_box(s.L, s.tilt, s.dim)
+    q = s.points if query_points is None else query_points
+    if exclude_ii is None:
+        exclude_ii = query_points is None
+    # oracle over the selected query rows; exclude_ii needs true indices, so
+    # pass all points and keep the wanted rows (small inputs) or recompute per row
+    csr_off, csr_idx, csr_r2 = [0], [], []
+    for qi in rows:
+        o, i, r = oracle.ball_query(ob, s.points, r_max, query_points=q[qi:qi + 1], exclude_ii=False)
+        if exclude_ii:
+            keep = i != qi
+            i, r = i[keep], r[keep]
+        csr_idx.append(i)
+        csr_r2.append(r)
+        csr_off.append(csr_off[-1] + len(i))
+    return (np.array(csr_off), np.concatenate(csr_idx) if csr_idx else np.zeros(0, np.int32),
+            np.concatenate(csr_r2) if csr_r2 else np.zeros(0))
+
+
+def _oracle_all(s, r_max, query_points=None, exclude_ii=None):
+    ob = oracle.make_box(s.L, s.tilt, s.dim)
+    return oracle.ball_query(ob, s.points, r_max, query_points=query_points, exclude_ii=exclude_ii)
+
+
+def test_small_uniform_ball_and_rdf(ppa):
+    s = workloads.small_uniform()
+    box = _box(s)
+    counts, nl = ppa.rdf_counts(box, s.points, 100, 3.0, neighbor_list=True)
+    n = s.points.shape[0]
+    ref = _oracle_all(s, 3.0)
+    n_cert, n_amb = check_rows(nl, ref, range(n), 3.0)
+    assert n_cert > 300000
+    assert n_cert <= nl.n_pairs <= n_cert + n_amb
+    off = nl.offsets.cpu().numpy()
+    assert off[-1] == nl.n_pairs
+    cnt = nl.counts.cpu().numpy()
+    assert off[0] == 0 and np.all(np.diff(off) == cnt)
+    lo, hi, amb = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), s.points, 100, 3.0)
+    g = counts.cpu().numpy()
+    check_hist(g, lo, hi)
+    assert g.sum() == nl.n_pairs
+    # the same histogram from the stored list
+    g2 = ppa.rdf_from_nlist(nl, 100, 3.0).cpu().numpy()
+    np.testing.assert_array_equal(g, g2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_triclinic_boxes(ppa, dim, seed):
+    rng = np.random.default_rng(100 + 10 * dim + seed)
+    L = rng.uniform(6.0, 14.0, 3)
+    tilt = rng.uniform(-0.5, 0.5, 3)
+    if dim == 2:
+        L[2] = 1.0
+        tilt[1:] = 0
+    n = int(rng.integers(50, 3000))
+    s = workloads.uniform(n, 1.0, seed=seed, dim=dim, tilt=tuple(tilt), L=tuple(L))
+    half = 0.5 * brute.perpendicular_widths(tuple(L), tuple(tilt), dim)[:dim].min()
+    for frac in (0.3, 0.7, 0.99):
+        r_max = float(frac * half)
+        box = _box(s)
+        nl = ppa.query_ball(box, s.points, r_max)
+        check_rows(nl, _oracle_all(s, r_max), range(n), r_max)
+        bins = int(rng.integers(1, 200))
+        r_min = float(rng.uniform(0, 0.5 * r_max))
+        c = ppa.rdf_counts(box, s.points, bins, r_max, r_min=r_min).cpu().numpy()
+        lo, hi, amb = oracle.rdf_counts(oracle.make_box(s.L, s.tilt, dim), s.points, bins, r_max,
+                                        r_min)
+        check_hist(c, lo, hi)
+
+
+def test_separate_query_points(ppa):
+    rng = np.random.default_rng(7)
+    s = workloads.uniform(2500, 0.9, seed=8, tilt=(0.3, -0.2, 0.1))
+    A = workloads.lattice_vectors(s.L, s.tilt)
+    q = (rng.uniform(-1.5, 1.5, (700, 3)) @ A.T).astype(np.float32)  # also outside the box
+    box = _box(s)
+    for excl in (False, True):
+        nl = ppa.query_ball(box, s.points, 2.2, query_points=q, exclude_ii=excl)
+        ob = oracle.make_box(s.L, s.tilt)
+        ref = oracle.ball_query(ob, s.points, 2.2, query_points=q, exclude_ii=excl)
+        check_rows(nl, ref, range(700), 2.2)
+        c = ppa.rdf_counts(box, s.points, 50, 2.2, query_points=q, exclude_ii=excl).cpu().numpy()
+        lo, hi, _ = oracle.rdf_counts(ob, s.points, 50, 2.2, query_points=q, exclude_ii=excl)
+        check_hist(c, lo, hi)
+
+
+def test_self_pairs_and_coincident_points(ppa):
+    pts = np.zeros((5, 3), np.float32)
+    pts[3] = [1.0, 0, 0]
+    pts[4] = [1.0, 0, 0]
+    s = workloads.System((10.0, 10.0, 10.0), (0, 0, 0), 3, pts)
+    box = _box(s)
+    nl = ppa.query_ball(box, pts, 1.5, exclude_ii=False)
+    cnt = nl.counts.cpu().numpy()
+    assert cnt.tolist() == [5, 5, 5, 5, 5]
+    nl = ppa.query_ball(box, pts, 1.5)
+    assert nl.counts.cpu().numpy().tolist() == [4, 4, 4, 4, 4]
+    nl = ppa.query_ball(box, pts, 0.5)
+    assert nl.counts.cpu().numpy().tolist() == [2, 2, 2, 1, 1]
+
+
+def test_empty_and_tiny_inputs(ppa):
+    box = ppa.Box.cube(10.0)
+    nl = ppa.query_ball(box, np.zeros((0, 3), np.float32), 2.0)
+    assert nl.n_pairs == 0 and nl.offsets.cpu().numpy().tolist() == [0]
+    nl = ppa.query_ball(box, np.zeros((1, 3), np.float32), 2.0)
+    assert nl.n_pairs == 0
+    q = np.zeros((0, 3), np.float32)
+    nl = ppa.query_ball(box, np.ones((10, 3), np.float32), 2.0, query_points=q)
+    assert nl.n_pairs == 0 and nl.offsets.shape[0] == 1
+
+
+def test_dense_cluster_takes_streamed_path(ppa):
+    """More than 1024 candidates in a stencil: the streamed path must agree."""
+    rng = np.random.default_rng(5)
+    pts = rng.normal(0, 0.6, (3000, 3)).astype(np.float32)
+    s = workloads.System((20.0, 20.0, 20.0), (0.1, 0, 0), 3, pts)
+    box = _box(s)
+    counts, nl = ppa.rdf_counts(box, pts, 64, 1.9, neighbor_list=True)
+    rows = list(range(0, 3000, 7))
+    check_rows(nl, _oracle_rows(s, 1.9, rows), rows, 1.9)
+    lo, hi, _ = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), pts, 64, 1.9)
+    check_hist(counts.cpu().numpy(), lo, hi)
+
+
+def test_capacity_overflow_reported_then_retry(ppa):
+    import torch
+    s = workloads.small_uniform()
+    box = _box(s)
+    nl = ppa.query_ball(box, s.points, 3.0, capacity=10)  # binding retries with the exact size
+    rows = list(range(0, 4096, 5))
+    check_rows(nl, _oracle_rows(s, 3.0, rows), rows, 3.0)
+    # raw call: capacity 1 -> PPA_ECAPACITY with the true count reported
+    import ctypes
+    L = ppa.lib()
+    pts = torch.as_tensor(s.points).cuda()
+    n = pts.shape[0]
+    ws = ppa.Workspace()
+    wptr, wlen = ws.get(ppa.workspace_bytes(box, n, 0, 3.0, ppa.PPA_WS_NLIST))
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    pidx = torch.empty(1, dtype=torch.int32, device="cuda")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc = L.ppa_query_ball(ctypes.byref(box.c()), ctypes.c_void_p(pts.data_ptr()), n, None, n, 3.0, 1,
+                          0, wptr, wlen, ctypes.c_void_p(off.data_ptr()),
+                          ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(pidx.data_ptr()), None,
+                          1, ctypes.c_void_p(npairs.data_ptr()),
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    assert ws.status() == ppa.PPA_ECAPACITY
+    assert int(npairs.item()) == nl.n_pairs
+
+
+def test_nonfinite_input_reported(ppa):
+    s = workloads.small_uniform()
+    pts = s.points.copy()
+    pts[17, 1] = np.nan
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.query_ball(_box(s), pts, 3.0)
+    assert e.value.code == ppa.PPA_ENONFINITE
+
+
+def test_host_errors(ppa):
+    s = workloads.small_uniform()
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.query_ball(_box(s), s.points, 9.0)
+    assert e.value.code == ppa.PPA_ERANGE
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.rdf_counts(_box(s), s.points, 0, 3.0)
+    assert e.value.code == ppa.PPA_EINVAL
+
+
+def test_deterministic_rows(ppa):
+    s = workloads.small_uniform()
+    box = _box(s)
+    a = ppa.query_ball(box, s.points, 3.0)
+    b = ppa.query_ball(box, s.points, 3.0)
+    assert a.n_pairs == b.n_pairs
+    assert np.array_equal(a.offsets.cpu().numpy(), b.offsets.cpu().numpy())
+    assert np.array_equal(a.point_idx.cpu().numpy(), b.point_idx.cpu().numpy())
+    assert np.array_equal(a.dist.cpu().numpy(), b.dist.cpu().numpy())
+
+
+def test_large_fcc_sampled_rows_and_rdf(ppa):
+    """N = 1,048,576 noisy FCC in a tilted box, in the launch configuration the
+    benchmark times (one pass, list + fused RDF): sampled rows against the
+    oracle, and the full histogram against properties that hold at any size."""
+    import torch
+    s = workloads.large_fcc()
+    box = _box(s)
+    n = s.points.shape[0]
+    counts, nl = ppa.rdf_counts(box, s.points, 256, 2.5, neighbor_list=True)
+    rng = np.random.default_rng(2)
+    rows = np.unique(np.concatenate([rng.choice(n, 250, replace=False), [0, 1, n - 1, n // 2]]))
+    n_cert, n_amb = check_rows(nl, _oracle_rows(s, 2.5, rows), rows, 2.5)
+    assert n_cert > 60 * len(rows)
+    g = counts.cpu().numpy()
+    assert g.sum() == nl.n_pairs
+    np.testing.assert_array_equal(g, ppa.rdf_from_nlist(nl, 256, 2.5).cpu().numpy())
+    cnt = nl.counts.cpu().numpy()
+    assert cnt.sum() == nl.n_pairs
+    assert cnt.min() >= 50 and cnt.max() <= 100
+    # the histogram restricted to the sampled query rows against the oracle
+    q = s.points[rows]
+    sub = ppa.rdf_counts(box, s.points, 256, 2.5, query_points=q, exclude_ii=False).cpu().numpy()
+    lo, hi, _ = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), s.points, 256, 2.5,
+                                  query_points=q, exclude_ii=False)
+    # a query point sits on itself at r = 0, which falls in bin 0 for both
+    check_hist(sub, lo, hi)

@@ -1,0 +1,143 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+the header declares, and its host-side validation returns the documented
+codes before touching the device."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1906_06317_amd as ppa
+from tests import brute
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(ppa_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ppa.lib()
+    names = _declared()
+    assert {"ppa_query_ball", "ppa_rdf", "ppa_sync_status"} <= names
+    out = subprocess.run(["nm", "-D", "--defined-only", ppa._LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ppa_[a-z0-9_]+)$", out, flags=re.M))
+    assert names <= exported, names - exported
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_version():
+    assert "gfx950" in ppa.version()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_box_widths_match_geometry(dim):
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        L = tuple(rng.uniform(1, 10, 3))
+        tilt = tuple(rng.uniform(-0.8, 0.8, 3))
+        if dim == 2:
+            L = (L[0], L[1], 1.0)
+            tilt = (tilt[0], 0.0, 0.0)
+        w = ppa.Box(L, tilt, dim).widths()
+        ref = brute.perpendicular_widths(L, tilt, dim)
+        np.testing.assert_allclose(w[:dim], ref[:dim], rtol=1e-12)
+
+
+def test_box_from_matrix():
+    m = np.array([[4.0, 1.0, 0.5], [0.0, 5.0, -1.0], [0.0, 0.0, 2.0]])
+    b = ppa.Box.from_matrix(m)
+    np.testing.assert_allclose(b.L, (4, 5, 2))
+    np.testing.assert_allclose(b.tilt, (0.2, 0.25, -0.5))
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.Box.from_matrix(np.array([[1.0, 0, 0], [0.3, 1, 0], [0, 0, 1]]))
+    assert e.value.code == ppa.PPA_EBOX
+
+
+def test_workspace_bytes_and_range_check():
+    box = ppa.Box.cube(10.0)
+    small = ppa.workspace_bytes(box, 1000, 0, 2.0)
+    big = ppa.workspace_bytes(box, 100000, 0, 2.0)
+    assert 0 < small < big
+    assert ppa.workspace_bytes(box, 1000, 500, 2.0) > small
+    assert ppa.workspace_bytes(box, 1000, 0, 2.0, ppa.PPA_WS_NLIST) > small
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.workspace_bytes(box, 1000, 0, 5.0)  # = half the box width
+    assert e.value.code == ppa.PPA_ERANGE
+    tilted = ppa.Box((10.0, 10.0, 10.0), (0.9, 0.0, 0.0))
+    w = tilted.widths()
+    with pytest.raises(ppa.PPAError):
+        ppa.workspace_bytes(tilted, 10, 0, 0.5 * min(w) * 1.0001)
+    ppa.workspace_bytes(tilted, 10, 0, 0.5 * min(w) * 0.999)
+
+
+def _call_ball(box, n=10, nq=10, qpts=None, r=1.0, flags=0, ws=1 << 8, ws_bytes=1 << 40,
+               offsets=8, counts=8, pidx=8, cap=10, npairs=8):
+    L = ppa.lib()
+    cb = box.c() if box is not None else None
+    return L.ppa_query_ball(ctypes.byref(cb) if cb is not None else None, ctypes.c_void_p(64), n,
+                            qpts, nq, r, 1, flags, ctypes.c_void_p(ws), ws_bytes,
+                            ctypes.c_void_p(offsets) if offsets else None,
+                            ctypes.c_void_p(counts) if counts else None,
+                            ctypes.c_void_p(pidx) if pidx else None, None, cap,
+                            ctypes.c_void_p(npairs) if npairs else None, None)
+
+
+def test_query_argument_errors_before_any_device_work():
+    box = ppa.Box.cube(10.0)
+    assert _call_ball(None) == ppa.PPA_EINVAL
+    assert _call_ball(box, n=-1) == ppa.PPA_EINVAL
+    assert _call_ball(box, nq=5) == ppa.PPA_EINVAL                 # nq != n without query points
+    assert _call_ball(box, r=-1.0) == ppa.PPA_EINVAL
+    assert _call_ball(box, r=float("nan")) == ppa.PPA_EINVAL
+    assert _call_ball(box, flags=8) == ppa.PPA_EINVAL
+    assert _call_ball(box, offsets=0) == ppa.PPA_EINVAL
+    assert _call_ball(box, cap=-1) == ppa.PPA_EINVAL
+    assert _call_ball(box, r=6.0) == ppa.PPA_ERANGE
+    assert _call_ball(box, ws=0) == ppa.PPA_EWORKSPACE
+    assert _call_ball(box, ws=(1 << 8) + 4) == ppa.PPA_EWORKSPACE   # misaligned
+    assert _call_ball(box, ws_bytes=16) == ppa.PPA_EWORKSPACE
+    assert b"workspace" in ppa.lib().ppa_last_error()
+    bad = ppa.Box((10.0, -1.0, 10.0))
+    assert _call_ball(bad) == ppa.PPA_EBOX
+    bad = ppa.Box((10.0, 10.0, 10.0), (math.inf, 0, 0))
+    assert _call_ball(bad) == ppa.PPA_EBOX
+    bad = ppa.Box((10.0, 10.0, 10.0), (0, 0, 0), 4)
+    assert _call_ball(bad) == ppa.PPA_EINVAL
+
+
+def test_rdf_argument_errors():
+    L = ppa.lib()
+    box = ppa.Box.cube(10.0).c()
+    args = lambda bins, rmin, rmax, hist: L.ppa_rdf(
+        ctypes.byref(box), ctypes.c_void_p(64), 10, None, 10, bins, rmin, rmax, 1, 0,
+        ctypes.c_void_p(256), 1 << 40, ctypes.c_void_p(hist) if hist else None, None, None, None,
+        None, 0, None, None)
+    assert args(0, 0.0, 2.0, 8) == ppa.PPA_EINVAL
+    assert args(10, 2.0, 2.0, 8) == ppa.PPA_EINVAL
+    assert args(10, -1.0, 2.0, 8) == ppa.PPA_EINVAL
+    assert args(10, 0.0, 2.0, 0) == ppa.PPA_EINVAL
+    assert L.ppa_rdf_from_nlist(None, None, 0, 10, 0.0, 1.0, None, None) == ppa.PPA_EINVAL
+
+
+def test_binding_has_no_cpu_fallback():
+    """The product path imports nothing from the oracle."""
+    pkg = os.path.join(ROOT, "paper_1906_06317_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "liboracle" not in src, f
