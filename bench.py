@@ -68,8 +68,8 @@ def cpu_baseline(sysm, n_pairs_total, target_s):
         dt = time.perf_counter() - t
         return dt, int(idx.shape[0]) - nq  # drop each row's self pair at r = 0
 
-    dt, _ = run(16)
-    nq = int(min(n, max(16, 16 * target_s / max(dt, 1e-3))))
+    dt, _ = run(128)
+    nq = int(min(n, max(128, 128 * target_s / max(dt, 1e-3))))
     dt, pairs = run(nq)
     return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
             "kind": "oracle",

@@ -165,7 +165,7 @@ class Workspace:
     def get(self, nbytes):
         torch = _torch()
         if self.buf is None or self.nbytes < nbytes:
-            self.buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+            self.buf = torch.zeros(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
             base = self.buf.data_ptr()
             self.ptr = (base + 255) // 256 * 256
             self.nbytes = int(nbytes)

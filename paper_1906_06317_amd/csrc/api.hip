@@ -99,8 +99,12 @@ int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g)
     for (int k = 0; k < 3; ++k) g->n[k] = (int)nk[k];
     g->ncells = g->n[0] * g->n[1] * g->n[2];
     g->nsten = dim == 3 ? 27 : 9;
+    // slot 0 is the home cell: it swaps places with offset code 0
+    const int centre = g->nsten / 2;
     for (int s = 0; s < 27; ++s) {
-        double d[3] = {(double)(s % 3 - 1), (double)((s / 3) % 3 - 1), dim == 3 ? (double)(s / 9 - 1) : 0.0};
+        const int code = s == 0 ? centre : (s == centre ? 0 : s);
+        double d[3] = {(double)(code % 3 - 1), (double)((code / 3) % 3 - 1),
+                       dim == 3 ? (double)(code / 9 - 1) : 0.0};
         if (s >= g->nsten) d[0] = d[1] = d[2] = 0.0;
         double f[3] = {d[0] / g->n[0], d[1] / g->n[1], d[2] / g->n[2]};
         g->off[s][0] = (float)(b.M[0][0] * f[0] + b.M[0][1] * f[1] + b.M[0][2] * f[2]);
@@ -121,11 +125,11 @@ static void carve_cells(char* base, size_t& off, const Grid& g, int64_t n, CellL
     };
     cl->n = n;
     cl->cell_of = (int*)take(sizeof(int) * (size_t)n);
+    cl->slot = (int*)take(sizeof(int) * (size_t)n);
     cl->local = (float4*)take(sizeof(float4) * (size_t)n);
     cl->sorted = (float4*)take(sizeof(float4) * (size_t)n);
     cl->cell_count = (int*)take(sizeof(int) * (size_t)g.ncells);
     cl->cell_start = (int*)take(sizeof(int) * ((size_t)g.ncells + 1));
-    cl->cursor = (int*)take(sizeof(int) * (size_t)g.ncells);
     const size_t nf = scan_flag_count(g.ncells);
     cl->scan_flags = (unsigned long long*)take(sizeof(unsigned long long) * nf + 256);
     cl->scan_ticket = cl->scan_flags ? (int*)(cl->scan_flags + nf) : nullptr;
@@ -207,6 +211,31 @@ int check_cutoff(const BoxPrep& bp, double r)
     return PPA_OK;
 }
 
+// Whether the expanded in/out test |c|^2 - 2 c.q < r^2 - |q|^2 is accurate
+// enough in float32: its worst-case rounding error, for a query anywhere in
+// its cell (|q| <= the cell's centre-to-corner distance) and a candidate
+// near the cutoff (|c| <= |q| + r), must stay below half the parity band
+// (1e-5 r^2) so that every pair outside the band is decided exactly.
+bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r)
+{
+    double qmax = 0.0;
+    for (int sx = -1; sx <= 1; sx += 2)
+        for (int sy = -1; sy <= 1; sy += 2)
+            for (int sz = -1; sz <= 1; sz += 2) {
+                const double f[3] = {0.5 * sx / g.n[0], 0.5 * sy / g.n[1],
+                                     bp.dim == 3 ? 0.5 * sz / g.n[2] : 0.0};
+                const double x = bp.M[0][0] * f[0] + bp.M[0][1] * f[1] + bp.M[0][2] * f[2];
+                const double y = bp.M[1][1] * f[1] + bp.M[1][2] * f[2];
+                const double z = bp.M[2][2] * f[2];
+                qmax = fmax(qmax, sqrt(x * x + y * y + z * z));
+            }
+    const double cmax = qmax + r;
+    const double u = ldexp(1.0, -24);  // unit roundoff of float32
+    const double err = u * (3 * cmax * cmax + 3 * (cmax * cmax + 2 * cmax * qmax) +
+                            3 * qmax * qmax + (r * r + qmax * qmax));
+    return err <= 0.5e-5 * r * r;
+}
+
 int run_pairs(const QueryCall& c)
 {
     if (!c.pts && c.n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
@@ -251,16 +280,17 @@ int run_pairs(const QueryCall& c)
     if (c.qpts) launch_build_cells(c.qpts, W.qry, bp, g, W.status, s);
 
     PairArgs A{};
-    A.cand = W.pts.sorted;
+    A.cand = W.pts.local;
     A.cand_start = W.pts.cell_start;
-    A.qsorted = W.qry.sorted;
+    A.qsorted = W.qry.local;
     A.q_start = W.qry.cell_start;
     for (int k = 0; k < 3; ++k) A.geom.n[k] = g.n[k];
     A.geom.ncells = g.ncells;
     A.geom.nsten = g.nsten;
-    A.geom.center = g.nsten / 2;
+    A.geom.center = 0;
     memcpy(A.geom.off, g.off, sizeof(A.geom.off));
     A.geom.r2max = c.r_max * c.r_max;
+    A.geom.dot = expanded_test_ok(bp, g, c.r_max) ? 1 : 0;
     A.offsets = c.offsets;
     A.point_idx = c.point_idx;
     A.dist = c.dist;
@@ -270,7 +300,6 @@ int run_pairs(const QueryCall& c)
     A.bins = c.want_hist ? c.bins : 0;
     A.r_min = c.r_min;
     A.inv_dr = c.want_hist ? (float)((double)c.bins / ((double)c.r_max - (double)c.r_min)) : 0.f;
-    const int blocks = pair_grid_blocks(g.ncells);
     const int dim = bp.dim;
     const int excl = !c.exclude_ii ? 0 : (c.qpts ? 2 : 1);
 
@@ -278,13 +307,13 @@ int run_pairs(const QueryCall& c)
     if (c.want_nl) {
         A.counts = c.counts ? c.counts : W.qry_row_counts;
         record(pe.ev[0], s);
-        launch_count(A, dim, excl, blocks, s);
+        launch_count(A, dim, excl, s);
         record(pe.ev[1], s);
         launch_scan_i64_total(A.counts, c.offsets, c.nq, W.row_scan_flags, W.row_scan_ticket,
                               (unsigned long long*)c.n_pairs_dev, s);
     }
     record(pe.ev[2], s);
-    launch_fill(A, dim, excl, c.want_nl, c.want_hist, blocks, s);
+    launch_fill(A, dim, excl, c.want_nl, c.want_hist, s);
     record(pe.ev[3], s);
     return hip_check(hipGetLastError(), "kernel launch");
 }

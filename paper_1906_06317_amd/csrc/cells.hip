@@ -35,6 +35,7 @@ __global__ void zero_kernel(ZeroRanges z)
 // Cell index and cell-centred local coordinates, in float64.
 __global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ pts, int64_t n,
                                                      AssignBox B, int* __restrict__ cell_of,
+                                                     int* __restrict__ slot,
                                                      float4* __restrict__ local,
                                                      int* __restrict__ cell_count,
                                                      unsigned* __restrict__ status)
@@ -70,40 +71,38 @@ __global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ p
     const int cell = (c[2] * B.ni[1] + c[1]) * B.ni[0] + c[0];
     cell_of[i] = cell;
     local[i] = make_float4((float)x, (float)y, (float)z, __int_as_float((int)i));
-    atomicAdd(&cell_count[cell], 1);
+    slot[i] = atomicAdd(&cell_count[cell], 1);
 }
 
+// Place every point in its cell's run at the slot its atomic returned (the
+// order inside a run is arrival order, not yet deterministic).
 __global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int* __restrict__ cell_of,
+                                                      const int* __restrict__ slot,
                                                       const float4* __restrict__ local,
                                                       const int* __restrict__ cell_start,
-                                                      int* __restrict__ cursor,
-                                                      float4* __restrict__ sorted)
+                                                      float4* __restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int c = cell_of[i];
-    const int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
-    sorted[pos] = local[i];
+    out[cell_start[cell_of[i]] + slot[i]] = local[i];
 }
 
-// Order each cell's run by point index (insertion sort, one thread per cell).
-__global__ void __launch_bounds__(256) order_cells_kernel(int ncells,
-                                                          const int* __restrict__ cell_start,
-                                                          float4* __restrict__ sorted)
+// Order each cell's run by point index: every entry counts the entries of its
+// run with a smaller index (its rank) and moves there.
+__global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restrict__ cell_of,
+                                                   const int* __restrict__ cell_start,
+                                                   const float4* __restrict__ in,
+                                                   float4* __restrict__ out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float4 v = in[p];
+    const int id = __float_as_int(v.w);
+    const int c = cell_of[id];
     const int b = cell_start[c], e = cell_start[c + 1];
-    for (int i = b + 1; i < e; ++i) {
-        const float4 v = sorted[i];
-        const int key = __float_as_int(v.w);
-        int j = i - 1;
-        while (j >= b && __float_as_int(sorted[j].w) > key) {
-            sorted[j + 1] = sorted[j];
-            --j;
-        }
-        sorted[j + 1] = v;
-    }
+    int r = 0;
+    for (int j = b; j < e; ++j) r += __float_as_int(in[j].w) < id;
+    out[b + r] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -114,13 +113,14 @@ __global__ void __launch_bounds__(256) order_cells_kernel(int ncells,
 // prefix.  A status word packs the state in its top two bits (1 aggregate,
 // 2 inclusive prefix) and the value in the low 62.
 // ---------------------------------------------------------------------------
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = kScanTile / kScanThreads;
+constexpr int kScanThreads = 1024;
+// items per thread: 2 for short arrays (many tiles in flight), 16 for long
+// ones (few tiles, so the look-back stays within one window)
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
 
-template <typename Out>
+template <typename Out, int kScanItems>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restrict__ in,
                                                             Out* __restrict__ out, int64_t n,
                                                             unsigned long long* flags,
@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1);
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    constexpr int kTile = kScanThreads * kScanItems;
+    const int64_t base = tile * kTile + (int64_t)threadIdx.x * kScanItems;
     long long v[kScanItems];
     long long sum = 0;
 #pragma unroll
@@ -157,33 +158,42 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
         if (w < wv) warp_before += s_warp[w];
         block_total += s_warp[w];
     }
-    if (threadIdx.x == 0) {
-        long long prefix = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&flags[0], kFlagInc | (unsigned long long)block_total,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&flags[tile], kFlagAgg | (unsigned long long)block_total,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = tile - 1;
-            while (true) {
-                unsigned long long f;
-                do {
-                    f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                } while ((f >> 62) == 0);
-                prefix += (long long)(f & kValueMask);
-                if ((f >> 62) == 2) break;
-                --j;
-            }
+    if (wv == 0) {
+        // publish the aggregate, then look back 64 predecessors at a time
+        if (lane == 0)
             __hip_atomic_store(&flags[tile],
-                               kFlagInc | (unsigned long long)(prefix + block_total),
+                               (tile == 0 ? kFlagInc : kFlagAgg) | (unsigned long long)block_total,
                                __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long long prefix = 0;
+        int64_t win = tile - 1;  // predecessor examined by lane 0
+        while (win >= 0) {
+            const int64_t j = win - lane;
+            unsigned long long f = kFlagInc;  // before tile 0: an empty inclusive prefix
+            if (j >= 0) {
+                do {
+                    f = __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } while ((f >> 62) == 0);
+            }
+            const unsigned long long inc = __ballot((f >> 62) == 2);
+            const int stop = __ffsll((long long)inc) - 1;  // nearest inclusive prefix, if any
+            long long v = (long long)(f & kValueMask);
+            if (stop >= 0 && lane > stop) v = 0;
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+            prefix += v;
+            if (stop >= 0) break;
+            win -= kWave;
         }
-        s_prefix = prefix;
-        const int64_t ntiles = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
-        if (tile == ntiles - 1) {
-            out[n] = (Out)(prefix + block_total);
-            if (total_out) *total_out = (unsigned long long)(prefix + block_total);
+        if (lane == 0) {
+            if (tile != 0)
+                __hip_atomic_store(&flags[tile],
+                                   kFlagInc | (unsigned long long)(prefix + block_total),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = prefix;
+            const int64_t ntiles = n > 0 ? (n + kTile - 1) / kTile : 1;
+            if (tile == ntiles - 1) {
+                out[n] = (Out)(prefix + block_total);
+                if (total_out) *total_out = (unsigned long long)(prefix + block_total);
+            }
         }
     }
     __syncthreads();
@@ -198,9 +208,15 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
 
 }  // namespace
 
+constexpr int kSmallItems = 2;
+constexpr int kLargeItems = 16;
+constexpr int64_t kLargeFrom = 64LL * kScanThreads * kSmallItems;
+
+// Status words the scan of n items needs (one per tile of the small size).
 size_t scan_flag_count(int64_t n)
 {
-    int64_t t = (n + kScanTile - 1) / kScanTile;
+    const int64_t tile = (int64_t)kScanThreads * kSmallItems;
+    int64_t t = (n + tile - 1) / tile;
     return (size_t)(t < 1 ? 1 : t);
 }
 
@@ -208,9 +224,17 @@ template <typename Out>
 static void launch_scan(const int* in, Out* out, int64_t n, unsigned long long* flags, int* ticket,
                         unsigned long long* total, hipStream_t s)
 {
-    const int64_t tiles = (int64_t)scan_flag_count(n);
-    hipLaunchKernelGGL(scan_kernel<Out>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out,
-                       n, flags, ticket, total);
+    if (n < kLargeFrom) {
+        const int64_t tile = (int64_t)kScanThreads * kSmallItems;
+        const int64_t tiles = n > 0 ? (n + tile - 1) / tile : 1;
+        hipLaunchKernelGGL((scan_kernel<Out, kSmallItems>), dim3((unsigned)tiles),
+                           dim3(kScanThreads), 0, s, in, out, n, flags, ticket, total);
+    } else {
+        const int64_t tile = (int64_t)kScanThreads * kLargeItems;
+        const int64_t tiles = (n + tile - 1) / tile;
+        hipLaunchKernelGGL((scan_kernel<Out, kLargeItems>), dim3((unsigned)tiles),
+                           dim3(kScanThreads), 0, s, in, out, n, flags, ticket, total);
+    }
 }
 
 void launch_scan_i64(const int* in, int64_t* out, int64_t n, unsigned long long* flags, int* ticket,
@@ -237,11 +261,9 @@ void launch_zero(Workspace& ws, const Grid& g, bool separate_queries, void* extr
     add(ws.status, 256);  // status word and counters share the header
     const size_t nf = scan_flag_count(g.ncells);
     add(ws.pts.cell_count, sizeof(int) * (size_t)g.ncells);
-    add(ws.pts.cursor, sizeof(int) * (size_t)g.ncells);
     add(ws.pts.scan_flags, sizeof(unsigned long long) * nf + 256);
     if (separate_queries) {
         add(ws.qry.cell_count, sizeof(int) * (size_t)g.ncells);
-        add(ws.qry.cursor, sizeof(int) * (size_t)g.ncells);
         add(ws.qry.scan_flags, sizeof(unsigned long long) * nf + 256);
     }
     if (ws.row_scan_flags)
@@ -269,14 +291,16 @@ void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const 
     const unsigned blocks = (unsigned)((n + 255) / 256);
     if (n > 0)
         hipLaunchKernelGGL(assign_kernel, dim3(blocks), dim3(256), 0, s, pts, n, ab, cl.cell_of,
-                           cl.local, cl.cell_count, status);
+                           cl.slot, cl.local, cl.cell_count, status);
     launch_scan<int>(cl.cell_count, cl.cell_start, g.ncells, cl.scan_flags, cl.scan_ticket,
                      nullptr, s);
     if (n > 0) {
-        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.local,
-                           cl.cell_start, cl.cursor, cl.sorted);
-        hipLaunchKernelGGL(order_cells_kernel, dim3((g.ncells + 255) / 256), dim3(256), 0, s,
-                           g.ncells, cl.cell_start, cl.sorted);
+        // arrival order into `sorted`, then ranked by index back into `local`,
+        // which from here on holds the final cell-sorted points
+        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.slot,
+                           cl.local, cl.cell_start, cl.sorted);
+        hipLaunchKernelGGL(rank_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of,
+                           cl.cell_start, cl.sorted, cl.local);
     }
 }
 

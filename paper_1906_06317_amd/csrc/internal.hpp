@@ -11,9 +11,8 @@ namespace ppa {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;             // threads per workgroup for the pair kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kMaxSlots = 16;           // candidate slots a wave keeps in registers
+constexpr int kMaxSlots = 12;           // candidate slots a wave keeps in registers
 constexpr int kCandCap = kMaxSlots * kWave;
-constexpr int kScanTile = 2048;         // elements per workgroup in the prefix scans
 constexpr int kMaxLdsBins = 4096;       // histograms up to this size live in LDS
 
 // Device status bits (the status word in the workspace).
@@ -50,11 +49,12 @@ struct AssignBox {
 // One cell list (points or query points) inside the workspace.
 struct CellList {
     int* cell_of;        // [n]
-    float4* local;       // [n] position relative to its cell centre, w = index bits
-    float4* sorted;      // [n] `local` sorted by cell, then by index
+    int* slot;           // [n] arrival slot inside the cell
+    float4* local;       // [n] position relative to its cell centre, w = index bits;
+                         //     after the build: sorted by cell, then by index
+    float4* sorted;      // [n] scratch (arrival order inside each cell)
     int* cell_count;     // [ncells]  (zeroed, then counts)
     int* cell_start;     // [ncells + 1]
-    int* cursor;         // [ncells]
     unsigned long long* scan_flags;  // decoupled look-back state
     int* scan_ticket;
     int64_t n;
@@ -99,6 +99,7 @@ struct PairGeom {
     int center;          // stencil slot of the home cell itself
     float off[27][3];    // stencil offsets M (delta / n)
     float r2max;
+    int dot;             // 1: expanded in/out test (its error bound passed on the host)
 };
 
 struct PairArgs {
@@ -121,10 +122,8 @@ struct PairArgs {
 
 // excl: 0 keep i == j, 1 points query themselves (drop the query's own
 // entry), 2 separate query points (drop j == i by index).
-void launch_count(const PairArgs& a, int dim, int excl, int blocks, hipStream_t s);
-void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, int blocks,
-                 hipStream_t s);
-int pair_grid_blocks(int ncells);
+void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s);
+void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s);
 void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,
                            float r_min, float inv_dr, unsigned long long* hist, hipStream_t s);
 

@@ -8,19 +8,26 @@
 //   * every wavefront owns a contiguous run of home cells; workgroups are
 //     renumbered so the cells of one XCD are contiguous and its L2 sees the
 //     stencil overlap of neighbouring cells;
-//   * for a home cell, the 27 (2D: 9) stencil cells are gathered into up to
-//     kMaxSlots registers per lane, each candidate shifted by its stencil
-//     offset so it is relative to the home cell's centre;
-//   * each query point of the home cell (scalar registers) is tested against
-//     every candidate slot; the query's own entry is removed from the ballot
-//     with a scalar mask when points query themselves.
+//   * for a home cell, the 27 (2D: 9) stencil cells are gathered into NS
+//     64-wide slots held in registers, each candidate shifted by its stencil
+//     offset so it is relative to the home cell's centre; the code for each
+//     slot count NS is unrolled separately, so the slot loop has no branches;
+//   * the home cell's query points are prefetched 64 at a time into lanes
+//     and read into scalar registers one by one; each is tested against
+//     every slot with one ballot per slot.
+// The in/out test of a candidate c against query q is either the plain
+// |c - q|^2 < r_max^2 or, when the host has bounded its rounding error well
+// inside the parity band, the expanded |c|^2 - 2 c.q < r_max^2 - |q|^2 (three
+// FMAs against the query's scalars).  Both passes evaluate the same
+// expression, so they agree pair by pair; every reported distance and bin is
+// recomputed from the difference c - q.
 // The NeighborList takes two passes so rows land in query order without
 // atomics: count_kernel writes row lengths, a scan turns them into CSR
 // offsets, and fill_kernel compacts hits with ballot + mbcnt into a small
-// per-wavefront LDS list (whole rows) that is flushed densely: sqrt, the
+// per-wavefront LDS list of whole rows, flushed densely: the distance, the
 // histogram bin and coalesced stores for 64 hits per instruction.  The RDF
-// alone (no list) needs only the fill pass.  Home cells with more candidates
-// than fit in registers stream candidates from memory instead.
+// alone (no list) needs only the fill pass.  Stencils with more candidates
+// than the register slots hold are processed in chunks, writing directly.
 #include "internal.hpp"
 
 namespace ppa {
@@ -28,8 +35,10 @@ namespace ppa {
 namespace {
 
 constexpr float kFar = 1.0e18f;
-constexpr int kHitCap = 512;   // hits buffered per wavefront in the list-writing pass
-constexpr int kRows = 64;      // rows buffered per wavefront
+constexpr int kHitCap = 384;  // hits buffered per wavefront between flushes
+constexpr int kRows = 64;     // rows buffered per wavefront
+constexpr int kChunkSlots = 8;  // slots per chunk of an oversized stencil
+constexpr int kFillSlots = 10;  // register slots of the fill pass (it needs more registers)
 
 __device__ __forceinline__ unsigned lane_prefix(unsigned long long mask)
 {
@@ -43,6 +52,23 @@ __device__ __forceinline__ float uniformf(float v)
 {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
+
+__device__ __forceinline__ int lane_of(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+
+__device__ __forceinline__ float lane_off(float v, int t)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
+}
+
+__device__ __forceinline__ long long lane_of64(long long v, int t)
+{
+    const unsigned lo = (unsigned)lane_of((int)(unsigned)v, t);
+    const unsigned hi = (unsigned)lane_of((int)(v >> 32), t);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Square root by the hardware instruction (within 1 ulp).
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -81,6 +107,14 @@ __device__ __forceinline__ void wave_tiles(int ncells, int wv, int& t0, int& t1)
     t1 = uniform((int)((gw + 1) * ncells / nw));
 }
 
+// Stencil slot -> offset code d = (dx+1) + 3 (dy+1) + 9 (dz+1): the home
+// cell (centre code) is slot 0 and takes the place of code 0.
+__device__ __forceinline__ int stencil_code(int s, int nsten)
+{
+    const int centre = nsten / 2;
+    return s == 0 ? centre : (s == centre ? 0 : s);
+}
+
 // Stencil of home cell `tile`: per-offset starts and prefix counts in LDS;
 // returns the candidate count C (uniform).
 template <int DIM>
@@ -93,7 +127,9 @@ __device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int 
     const int cz = rest / G.n[1];
     int cnt = 0, st = 0;
     if (lane < G.nsten) {
-        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = DIM == 3 ? lane / 9 - 1 : 0;
+        // slot 0 is the home cell itself (offset code 13 in 3D, 4 in 2D)
+        const int code = stencil_code(lane, G.nsten);
+        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = DIM == 3 ? code / 9 - 1 : 0;
         int x = cx + dx, y = cy + dy, z = cz + dz;
         x += x < 0 ? G.n[0] : 0;
         x -= x >= G.n[0] ? G.n[0] : 0;
@@ -138,21 +174,153 @@ __device__ __forceinline__ void fetch(const PairIn& in, const PairGeom& G, const
     id = __float_as_int(v.w);
 }
 
-// Bit of the query's own entry among the candidates (self queries only):
-// it is entry (qi - q0) of the centre cell.
-__device__ __forceinline__ void self_bit(const StencilLds& S, const PairGeom& G, int qi, int q0,
-                                        int& slot, unsigned long long& keep)
+// One query point in scalar registers, with the constants of both tests.
+struct Query {
+    float x, y, z;
+    float m2x, m2y, m2z;  // -2 q
+    float thr;            // r_max^2 - |q|^2
+    int id;
+};
+
+template <int DIM>
+__device__ __forceinline__ Query make_query(float x, float y, float z, int id, float r2max)
 {
-    const int k = uniform(S.pre[G.center] + (qi - q0));
-    slot = k >> 6;
-    keep = ~(1ull << (k & 63));
+    Query q;
+    q.x = x;
+    q.y = y;
+    q.z = DIM == 3 ? z : 0.f;
+    q.m2x = -2.f * x;
+    q.m2y = -2.f * y;
+    q.m2z = -2.f * q.z;
+    q.thr = uniformf(r2max - dist2<DIM>(x, y, q.z));
+    q.id = id;
+    return q;
 }
+
+// The candidates of one home cell in NS register slots (entries past the
+// end are far away, so they never hit).
+template <int DIM, int NS>
+struct Slots {
+    float x[NS > 0 ? NS : 1], y[NS > 0 ? NS : 1], z[NS > 0 ? NS : 1];
+    float cc[NS > 0 ? NS : 1];  // |c|^2
+    int id[NS > 0 ? NS : 1];
+
+    __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
+                                         const float4* off, int k0, int C, int lane)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            x[s] = y[s] = z[s] = kFar;
+            id[s] = -1;
+            const int k = k0 + s * kWave + lane;
+            if (k < C) fetch<DIM>(in, G, S, off, k, x[s], y[s], z[s], id[s]);
+            cc[s] = dist2<DIM>(x[s], y[s], z[s]);
+        }
+    }
+    // the in/out test of slot s against q; identical in both passes
+    template <bool DOT>
+    __device__ __forceinline__ bool hit(int s, const Query& q, float r2max) const
+    {
+        if (DOT) {
+            float t = fmaf(x[s], q.m2x, cc[s]);
+            t = fmaf(y[s], q.m2y, t);
+            if (DIM == 3) t = fmaf(z[s], q.m2z, t);
+            return t < q.thr;
+        }
+        return dist2<DIM>(x[s] - q.x, y[s] - q.y, z[s] - q.z) < r2max;
+    }
+};
+
+// Query points of a tile, 64 at a time, one per lane.
+struct QueryChunk {
+    float4 q;
+    int n;
+
+    __device__ __forceinline__ void load(const PairIn& in, int first, int count, int lane)
+    {
+        n = uniform(min(kWave, count));
+        q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < n) q = in.qs[first + lane];
+    }
+    template <int DIM>
+    __device__ __forceinline__ Query get(int t, float r2max) const
+    {
+        return make_query<DIM>(lane_off(q.x, t), lane_off(q.y, t), lane_off(q.z, t),
+                               lane_of(__float_as_int(q.w), t), r2max);
+    }
+    __device__ __forceinline__ int my_id() const { return __float_as_int(q.w); }
+};
 
 // ---------------------------------------------------------------------------
 // Pass 1: row lengths.
 // ---------------------------------------------------------------------------
+// Hits of one query against NS slots (the query's own entry included).
+template <int DIM, int EXCL, int NS, bool DOT>
+__device__ __forceinline__ int count_hits(const Slots<DIM, NS>& c, const Query& q, float r2max)
+{
+    int n = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        bool h = c.template hit<DOT>(s, q, r2max);
+        if (EXCL == 2) h = h && c.id[s] != q.id;
+        n += __popcll(__ballot(h));
+    }
+    return n;
+}
+
+template <int DIM, int EXCL, int NS>
+__device__ __forceinline__ void count_tile(const PairIn& in, const PairGeom& G,
+                                           const StencilLds& S, const float4* off, int C, int q0,
+                                           int q1, int lane, int32_t* __restrict__ counts)
+{
+    Slots<DIM, NS> c;
+    c.load(in, G, S, off, 0, C, lane);
+    const float r2max = G.r2max;
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        QueryChunk Q;
+        Q.load(in, c0, q1 - c0, lane);
+        int cnt_v = 0;
+        for (int t = 0; t < Q.n; ++t) {
+            const Query q = Q.get<DIM>(t, r2max);
+            int n = G.dot ? count_hits<DIM, EXCL, NS, true>(c, q, r2max)
+                          : count_hits<DIM, EXCL, NS, false>(c, q, r2max);
+            // a point querying itself always finds its own entry, at r = 0
+            if (EXCL == 1) n -= 1;
+            cnt_v = lane == t ? n : cnt_v;
+        }
+        if (lane < Q.n) counts[Q.my_id()] = cnt_v;
+    }
+}
+
+// Stencils too large for the register slots: candidate chunks of
+// kChunkSlots slots, each loaded once per 64 queries.
 template <int DIM, int EXCL>
-__global__ void __launch_bounds__(kBlock) count_kernel(const PairIn in, const PairGeom G,
+__device__ __forceinline__ void count_chunked(const PairIn& in, const PairGeom& G,
+                                              const StencilLds& S, const float4* off, int C,
+                                              int q0, int q1, int lane,
+                                              int32_t* __restrict__ counts)
+{
+    const float r2max = G.r2max;
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        QueryChunk Q;
+        Q.load(in, c0, q1 - c0, lane);
+        int cnt_v = EXCL == 1 ? -1 : 0;
+        for (int k0 = 0; k0 < C; k0 += kChunkSlots * kWave) {
+            Slots<DIM, kChunkSlots> c;
+            c.load(in, G, S, off, k0, C, lane);
+            for (int t = 0; t < Q.n; ++t) {
+                const Query q = Q.get<DIM>(t, r2max);
+                const int n = G.dot ? count_hits<DIM, EXCL, kChunkSlots, true>(c, q, r2max)
+                                    : count_hits<DIM, EXCL, kChunkSlots, false>(c, q, r2max);
+                cnt_v += lane == t ? n : 0;
+            }
+        }
+        if (lane < Q.n) counts[Q.my_id()] = cnt_v;
+    }
+}
+
+template <int DIM, int EXCL>
+__global__ void __launch_bounds__(kBlock, 5) count_kernel(const PairIn in, const PairGeom G,
                                                        int32_t* __restrict__ counts)
 {
     __shared__ float4 s_off[27];
@@ -166,65 +334,19 @@ __global__ void __launch_bounds__(kBlock) count_kernel(const PairIn in, const Pa
     __syncthreads();
     int t0, t1;
     wave_tiles(G.ncells, wv, t0, t1);
-    const float r2max = G.r2max;
     for (int tile = t0; tile < t1; ++tile) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
         const int C = stencil<DIM>(in, G, tile, lane, S);
-        if (C <= kCandCap) {
-            float rx[kMaxSlots], ry[kMaxSlots], rz[kMaxSlots];
-            int rid[kMaxSlots];
-#pragma unroll
-            for (int s = 0; s < kMaxSlots; ++s) {
-                rx[s] = ry[s] = rz[s] = kFar;
-                rid[s] = -1;
-                if (s * kWave < C) {
-                    const int k = s * kWave + lane;
-                    if (k < C) fetch<DIM>(in, G, S, s_off, k, rx[s], ry[s], rz[s], rid[s]);
-                }
-            }
-            for (int qi = q0; qi < q1; ++qi) {
-                const float4 q = in.qs[qi];
-                const float qx = uniformf(q.x), qy = uniformf(q.y), qz = uniformf(q.z);
-                const int qid = uniform(__float_as_int(q.w));
-                int sslot = -1;
-                unsigned long long keep = ~0ull;
-                if (EXCL == 1) self_bit(S, G, qi, q0, sslot, keep);
-                int c = 0;
-#pragma unroll
-                for (int s = 0; s < kMaxSlots; ++s) {
-                    if (s * kWave < C) {
-                        const float r2 = dist2<DIM>(rx[s] - qx, ry[s] - qy, rz[s] - qz);
-                        bool hit = r2 < r2max;
-                        if (EXCL == 2) hit = hit && rid[s] != qid;
-                        unsigned long long m = __ballot(hit);
-                        if (EXCL == 1) m &= (s == sslot) ? keep : ~0ull;
-                        c += __popcll(m);
-                    }
-                }
-                if (lane == 0) counts[qid] = c;
-            }
-        } else {
-            for (int qi = q0; qi < q1; ++qi) {
-                const float4 q = in.qs[qi];
-                const float qx = uniformf(q.x), qy = uniformf(q.y), qz = uniformf(q.z);
-                const int qid = uniform(__float_as_int(q.w));
-                int c = 0;
-                for (int k0 = 0; k0 < C; k0 += kWave) {
-                    const int k = k0 + lane;
-                    bool hit = false;
-                    if (k < C) {
-                        float x, y, z;
-                        int id;
-                        fetch<DIM>(in, G, S, s_off, k, x, y, z, id);
-                        hit = dist2<DIM>(x - qx, y - qy, z - qz) < r2max &&
-                              !(EXCL != 0 && id == qid);
-                    }
-                    c += __popcll(__ballot(hit));
-                }
-                if (lane == 0) counts[qid] = c;
-            }
+        const int ns = (C + kWave - 1) / kWave;
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: count_tile<DIM, EXCL, N>(in, G, S, s_off, C, q0, q1, lane, counts); break;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
+#undef PPA_CASE
+        default: count_chunked<DIM, EXCL>(in, G, S, s_off, C, q0, q1, lane, counts);
         }
     }
 }
@@ -244,17 +366,256 @@ struct FillOut {
     float inv_dr;
 };
 
+// Per-wavefront LDS of the fill pass.  With a list, a hit keeps the
+// candidate's coordinates (its exact distance is recomputed at the flush)
+// and rows are whole; for the histogram alone, a hit keeps only its exact
+// r^2 from the difference form.
 template <bool NL>
-struct FillLds {
-    int id[NL ? kHitCap : 1];
-    float r2[NL ? kHitCap : kCandCap];
-    unsigned char row[NL ? kHitCap : 1];
-    long long base[NL ? kRows : 1];   // offsets[q] - start of the row in the buffer
+struct FillLds;
+
+template <>
+struct FillLds<true> {
+    float4 hit[kHitCap];               // candidate xyz relative to the home centre, index bits
+    float4 rq[kRows];                  // each non-empty row's query xyz, index bits
+    long long base[kRows];             // offsets[q] - first buffered hit of the row
+    unsigned long long starts[kHitCap / 64];  // bit e: a non-empty row starts at hit e
     StencilLds st;
 };
 
+template <>
+struct FillLds<false> {
+    float r2[kCandCap];
+    StencilLds st;
+};
+
+// Per-wavefront state of the fill pass.
 template <int DIM, int EXCL, bool NL, bool HIST>
-__global__ void __launch_bounds__(kBlock) fill_kernel(const PairIn in, const PairGeom G,
+struct Filler {
+    FillLds<NL>& W;
+    const FillOut O;
+    unsigned* hist_lds;  // NULL: bin straight into O.hist
+    int lane;
+    int nh;     // hits buffered
+    int nrows;  // rows buffered
+    int selfs;  // own entries binned by the histogram-only path (all at r = 0)
+    bool over;
+
+    __device__ Filler(FillLds<NL>& w, const FillOut& o, unsigned* h, int l)
+        : W(w), O(o), hist_lds(h), lane(l), nh(0), nrows(0), selfs(0), over(false)
+    {
+    }
+
+    __device__ __forceinline__ void bin(float r)
+    {
+        const float t = (r - O.r_min) * O.inv_dr;
+        if (t >= 0.f && t < (float)O.bins) {
+            const int b = min((int)t, O.bins - 1);
+            if (hist_lds)
+                atomicAdd(&hist_lds[b], 1u);
+            else
+                atomicAdd(&O.hist[b], 1ull);
+        }
+    }
+    __device__ __forceinline__ void emit(long long dst, int id, float r)
+    {
+        if (dst < O.capacity) {
+            O.point_idx[dst] = id;
+            if (O.dist) O.dist[dst] = r;
+        } else {
+            over = true;
+        }
+    }
+    // Closes the row of query q that started at buffer position rs: a row
+    // with hits gets a record and its start bit (lane 0 writes them).
+    __device__ __forceinline__ void close_row(const Query& q, long long rbase, int rs)
+    {
+        if constexpr (NL) {
+            if (nh > rs) {
+                if (lane == 0) {
+                    W.rq[nrows] = make_float4(q.x, q.y, q.z, __int_as_float(q.id));
+                    W.base[nrows] = rbase - rs;
+                    W.starts[rs >> 6] |= 1ull << (rs & 63);
+                }
+                ++nrows;
+            }
+        }
+    }
+    // Emits every buffered hit: exact distance, list store and histogram bin.
+    // The row of hit e is the number of row starts at or before e, minus one.
+    __device__ __forceinline__ void flush()
+    {
+        wave_sync();
+        if constexpr (NL) {
+            int before = 0;  // row starts in earlier 64-hit blocks
+            for (int e0 = 0; e0 < nh; e0 += kWave) {
+                const unsigned long long bm = W.starts[e0 >> 6];
+                const int e = e0 + lane;
+                const int r = before + (int)lane_prefix(bm) + (int)((bm >> lane) & 1ull) - 1;
+                before += __popcll(bm);
+                if (e < nh) {
+                    const float4 h = W.hit[e];
+                    const float4 q = W.rq[r];
+                    const float d = fast_sqrt(dist2<DIM>(h.x - q.x, h.y - q.y, h.z - q.z));
+                    emit(W.base[r] + e, __float_as_int(h.w), d);
+                    if (HIST) bin(d);
+                }
+            }
+            if (lane < kHitCap / 64) W.starts[lane] = 0ull;
+        } else {
+            for (int e = lane; e < nh; e += kWave) bin(fast_sqrt(W.r2[e]));
+        }
+        nh = 0;
+        nrows = 0;
+        wave_sync();
+    }
+
+    // Buffers the hits of query q against NS slots.  For a point querying
+    // itself, its own entry is lane `self` of slot 0 (the home cell comes
+    // first in the stencil and lists its points in query order); BY_ID drops
+    // the entry with the query's index instead (separate query points, or a
+    // home cell too full for the lane rule).
+    template <int NS, bool DOT, bool BY_ID>
+    __device__ __forceinline__ void buffer_hits(const Slots<DIM, NS>& c, const Query& q,
+                                                float r2max, int self)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if constexpr (NL) {
+                bool h = c.template hit<DOT>(s, q, r2max);
+                if (BY_ID) h = h && c.id[s] != q.id;
+                if (!BY_ID && EXCL == 1 && s == 0) h = h && lane != self;
+                const unsigned long long m = __ballot(h);
+                if (h) {
+                    float4* dst = &W.hit[nh];
+                    dst[lane_prefix(m)] =
+                        make_float4(c.x[s], c.y[s], c.z[s], __int_as_float(c.id[s]));
+                }
+                nh += __popcll(m);
+            } else {
+                const float r2 = dist2<DIM>(c.x[s] - q.x, c.y[s] - q.y, c.z[s] - q.z);
+                bool h = r2 < r2max;
+                if (EXCL == 2) h = h && c.id[s] != q.id;
+                const unsigned long long m = __ballot(h);
+                if (h) W.r2[nh + (int)lane_prefix(m)] = r2;
+                nh += __popcll(m);
+            }
+        }
+        // the histogram-only path keeps a point's own entry (r = 0) and
+        // removes it from bin 0 at the end
+        if (!NL && EXCL == 1) ++selfs;
+    }
+    // Writes the hits of query q against NS slots straight to the outputs,
+    // at rbase + w onwards.
+    template <int NS, bool DOT>
+    __device__ __forceinline__ void direct_hits(const Slots<DIM, NS>& c, const Query& q,
+                                                float r2max, long long rbase, int& w)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            bool h = c.template hit<DOT>(s, q, r2max);
+            if (EXCL != 0) h = h && c.id[s] != q.id;
+            const unsigned long long m = __ballot(h);
+            if (h) {
+                const float d = fast_sqrt(dist2<DIM>(c.x[s] - q.x, c.y[s] - q.y, c.z[s] - q.z));
+                if (NL) emit(rbase + w + (int)lane_prefix(m), c.id[s], d);
+                if (HIST) bin(d);
+            }
+            w += __popcll(m);
+        }
+    }
+};
+
+template <int DIM, int EXCL, bool NL, bool HIST, int NS>
+__device__ __forceinline__ void fill_tile(const PairIn& in, const PairGeom& G, const StencilLds& S,
+                                          const float4* off, int C, int q0, int q1,
+                                          Filler<DIM, EXCL, NL, HIST>& F)
+{
+    const int lane = F.lane;
+    Slots<DIM, NS> c;
+    c.load(in, G, S, off, 0, C, lane);
+    const float r2max = G.r2max;
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        QueryChunk Q;
+        Q.load(in, c0, q1 - c0, lane);
+        long long rb_v = 0;
+        int rl_v = 0;
+        if (NL && lane < Q.n) {
+            rb_v = F.O.offsets[Q.my_id()];
+            rl_v = (int)(F.O.offsets[Q.my_id() + 1] - rb_v);
+        }
+        for (int t = 0; t < Q.n; ++t) {
+            const Query q = Q.get<DIM>(t, r2max);
+            long long rbase = 0;
+            // entries this query puts in the buffer: its row, plus its own
+            // entry when it is one of the points (dropped at the flush); for
+            // the histogram alone, at most every candidate
+            int need = C;
+            if (NL) {
+                rbase = lane_of64(rb_v, t);
+                need = lane_of(rl_v, t);
+            }
+            const int cap = NL ? kHitCap : kCandCap;
+            // position of the query's own entry in slot 0 (home cell first)
+            const int self = (c0 - q0) + t < kWave ? (c0 - q0) + t : -1;
+            if (need <= cap) {
+                if (F.nh + need > cap || (NL && F.nrows == kRows)) F.flush();
+                const int rs = F.nh;
+                const bool by_id = EXCL == 2 || (EXCL == 1 && self < 0);
+                if (NL && G.dot) {
+                    if (by_id)
+                        F.template buffer_hits<NS, true, true>(c, q, r2max, self);
+                    else
+                        F.template buffer_hits<NS, true, false>(c, q, r2max, self);
+                } else {
+                    if (by_id)
+                        F.template buffer_hits<NS, false, true>(c, q, r2max, self);
+                    else
+                        F.template buffer_hits<NS, false, false>(c, q, r2max, self);
+                }
+                F.close_row(q, rbase, rs);
+            } else {
+                int w = 0;
+                if (G.dot)
+                    F.template direct_hits<NS, true>(c, q, r2max, rbase, w);
+                else
+                    F.template direct_hits<NS, false>(c, q, r2max, rbase, w);
+            }
+        }
+    }
+}
+
+template <int DIM, int EXCL, bool NL, bool HIST>
+__device__ __forceinline__ void fill_chunked(const PairIn& in, const PairGeom& G,
+                                             const StencilLds& S, const float4* off, int C,
+                                             int q0, int q1, Filler<DIM, EXCL, NL, HIST>& F)
+{
+    const int lane = F.lane;
+    const float r2max = G.r2max;
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        QueryChunk Q;
+        Q.load(in, c0, q1 - c0, lane);
+        long long rb_v = 0;
+        if (NL && lane < Q.n) rb_v = F.O.offsets[Q.my_id()];
+        int w_v = 0;  // entries written so far, per query
+        for (int k0 = 0; k0 < C; k0 += kChunkSlots * kWave) {
+            Slots<DIM, kChunkSlots> c;
+            c.load(in, G, S, off, k0, C, lane);
+            for (int t = 0; t < Q.n; ++t) {
+                const Query q = Q.get<DIM>(t, r2max);
+                const long long rbase = NL ? lane_of64(rb_v, t) : 0;
+                int w = lane_of(w_v, t);
+                if (G.dot)
+                    F.template direct_hits<kChunkSlots, true>(c, q, r2max, rbase, w);
+                else
+                    F.template direct_hits<kChunkSlots, false>(c, q, r2max, rbase, w);
+                w_v = lane == t ? w : w_v;
+            }
+        }
+    }
+}
+
+template <int DIM, int EXCL, bool NL, bool HIST>
+__global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const PairGeom G,
                                                       const FillOut O)
 {
     extern __shared__ unsigned s_hist[];
@@ -262,8 +623,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(const PairIn in, const Pai
     __shared__ FillLds<NL> s_w[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
-    FillLds<NL>& W = s_w[wv];
-    StencilLds& S = W.st;
+    StencilLds& S = s_w[wv].st;
     const bool lds_hist = HIST && O.bins <= kMaxLdsBins;
     if (threadIdx.x < 27)
         s_off[threadIdx.x] = make_float4(G.off[threadIdx.x][0], G.off[threadIdx.x][1],
@@ -272,146 +632,37 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(const PairIn in, const Pai
         for (int b = threadIdx.x; b < O.bins; b += kBlock) s_hist[b] = 0u;
     __syncthreads();
 
-    auto bin = [&](float r) {
-        const float t = (r - O.r_min) * O.inv_dr;
-        if (t >= 0.f) {
-            int b = (int)t;
-            b = b < O.bins ? b : O.bins - 1;
-            if (lds_hist)
-                atomicAdd(&s_hist[b], 1u);
-            else
-                atomicAdd(&O.hist[b], 1ull);
-        }
-    };
-    auto emit = [&](long long dst, int id, float r) {
-        if (dst < O.capacity) {
-            O.point_idx[dst] = id;
-            if (O.dist) O.dist[dst] = r;
-            return false;
-        }
-        return true;
-    };
-
+    if constexpr (NL) {
+        if (lane < kHitCap / 64) s_w[wv].starts[lane] = 0ull;
+        wave_sync();
+    }
+    Filler<DIM, EXCL, NL, HIST> F(s_w[wv], O, lds_hist ? s_hist : nullptr, lane);
     int t0, t1;
     wave_tiles(G.ncells, wv, t0, t1);
-    const float r2max = G.r2max;
-    int nh = 0, nrows = 0;
-    bool over = false;
-
-    auto flush = [&]() {
-        wave_sync();
-        for (int e = lane; e < nh; e += kWave) {
-            const float r = __fsqrt_rn(W.r2[e]);
-            if (NL) over |= emit(W.base[W.row[e]] + e, W.id[e], r);
-            if (HIST) bin(r);
-        }
-        nh = 0;
-        nrows = 0;
-        wave_sync();
-    };
-
     for (int tile = t0; tile < t1; ++tile) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
         const int C = stencil<DIM>(in, G, tile, lane, S);
-        if (C <= kCandCap) {
-            float rx[kMaxSlots], ry[kMaxSlots], rz[kMaxSlots];
-            int rid[kMaxSlots];
-#pragma unroll
-            for (int s = 0; s < kMaxSlots; ++s) {
-                rx[s] = ry[s] = rz[s] = kFar;
-                rid[s] = -1;
-                if (s * kWave < C) {
-                    const int k = s * kWave + lane;
-                    if (k < C) fetch<DIM>(in, G, S, s_off, k, rx[s], ry[s], rz[s], rid[s]);
-                }
-            }
-            for (int qi = q0; qi < q1; ++qi) {
-                const float4 q = in.qs[qi];
-                const float qx = uniformf(q.x), qy = uniformf(q.y), qz = uniformf(q.z);
-                const int qid = uniform(__float_as_int(q.w));
-                int sslot = -1;
-                unsigned long long keep = ~0ull;
-                if (EXCL == 1) self_bit(S, G, qi, q0, sslot, keep);
-                long long rbase = 0;
-                int len = C;
-                if (NL) {
-                    rbase = O.offsets[qid];
-                    len = (int)(O.offsets[qid + 1] - rbase);
-                }
-                const int cap = NL ? kHitCap : kCandCap;
-                const bool direct = len > cap;  // a row longer than the buffer: write it directly
-                if (nh + len > cap || (NL && nrows == kRows) || (direct && nh > 0)) flush();
-                const int rs = nh;
-                int w = 0;
-#pragma unroll
-                for (int s = 0; s < kMaxSlots; ++s) {
-                    if (s * kWave < C) {
-                        const float r2 = dist2<DIM>(rx[s] - qx, ry[s] - qy, rz[s] - qz);
-                        bool hit = r2 < r2max;
-                        if (EXCL == 2) hit = hit && rid[s] != qid;
-                        unsigned long long m = __ballot(hit);
-                        if (EXCL == 1) m &= (s == sslot) ? keep : ~0ull;
-                        const bool mine = (m >> lane) & 1ull;
-                        if (!direct) {
-                            if (mine) {
-                                const int pos = nh + (int)lane_prefix(m);
-                                W.r2[pos] = r2;
-                                if (NL) {
-                                    W.id[pos] = rid[s];
-                                    W.row[pos] = (unsigned char)nrows;
-                                }
-                            }
-                            nh += __popcll(m);
-                        } else {
-                            if (mine) {
-                                const float r = __fsqrt_rn(r2);
-                                if (NL) over |= emit(rbase + w + (int)lane_prefix(m), rid[s], r);
-                                if (HIST) bin(r);
-                            }
-                            w += __popcll(m);
-                        }
-                    }
-                }
-                if (NL && !direct) {
-                    if (lane == 0) W.base[nrows] = rbase - rs;
-                    ++nrows;
-                }
-            }
-        } else {
-            // oversized stencil: stream the candidates from memory, writing directly
-            if (nh > 0) flush();
-            for (int qi = q0; qi < q1; ++qi) {
-                const float4 q = in.qs[qi];
-                const float qx = uniformf(q.x), qy = uniformf(q.y), qz = uniformf(q.z);
-                const int qid = uniform(__float_as_int(q.w));
-                const long long rbase = NL ? O.offsets[qid] : 0;
-                int w = 0;
-                for (int k0 = 0; k0 < C; k0 += kWave) {
-                    const int k = k0 + lane;
-                    bool hit = false;
-                    float r2 = 0.f;
-                    int id = -1;
-                    if (k < C) {
-                        float x, y, z;
-                        fetch<DIM>(in, G, S, s_off, k, x, y, z, id);
-                        r2 = dist2<DIM>(x - qx, y - qy, z - qz);
-                        hit = r2 < r2max && !(EXCL != 0 && id == qid);
-                    }
-                    const unsigned long long m = __ballot(hit);
-                    if (hit) {
-                        const float r = __fsqrt_rn(r2);
-                        if (NL) over |= emit(rbase + w + (int)lane_prefix(m), id, r);
-                        if (HIST) bin(r);
-                    }
-                    w += __popcll(m);
-                }
-            }
+        const int ns = (C + kWave - 1) / kWave;
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: fill_tile<DIM, EXCL, NL, HIST, N>(in, G, S, s_off, C, q0, q1, F); break;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
+#undef PPA_CASE
+            static_assert(kFillSlots == 10, "the cases above cover 0..kFillSlots");
+        default: fill_chunked<DIM, EXCL, NL, HIST>(in, G, S, s_off, C, q0, q1, F);
         }
     }
-    if (nh > 0) flush();
-    if (NL && __ballot(over) && lane == 0) atomicOr(O.status, kStatusCapacity);
+    if (F.nh > 0) F.flush();
+    if (NL && __ballot(F.over) && lane == 0) atomicOr(O.status, kStatusCapacity);
+    if (!NL && EXCL == 1 && F.selfs > 0 && O.r_min <= 0.f && lane == 0) {
+        if (lds_hist)
+            atomicSub(&s_hist[0], (unsigned)F.selfs);
+        else
+            atomicAdd(&O.hist[0], (unsigned long long)(-(long long)F.selfs));
+    }
 
     __syncthreads();
     if (lds_hist)
@@ -437,14 +688,12 @@ __global__ void __launch_bounds__(256) hist_from_dist_kernel(const float* __rest
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < np;
          e += (int64_t)gridDim.x * blockDim.x) {
         const float t = (dist[e] - r_min) * inv_dr;
-        if (t >= 0.f) {
-            int b = (int)t;
-            if (b < bins) {
-                if (lds_hist)
-                    atomicAdd(&s_hist[b], 1u);
-                else
-                    atomicAdd(&hist[b], 1ull);
-            }
+        if (t >= 0.f && t < (float)bins) {
+            const int b = min((int)t, bins - 1);
+            if (lds_hist)
+                atomicAdd(&s_hist[b], 1u);
+            else
+                atomicAdd(&hist[b], 1ull);
         }
     }
     __syncthreads();
@@ -455,27 +704,47 @@ __global__ void __launch_bounds__(256) hist_from_dist_kernel(const float* __rest
         }
 }
 
-template <int DIM, int EXCL>
-void launch_count_t(const PairIn& in, const PairGeom& g, int32_t* counts, int blocks,
-                    hipStream_t s)
+// Workgroups for a persistent launch of `kernel`: as many as fit on the
+// device at once, at least one home cell per wavefront, a multiple of 8.
+template <typename K>
+int resident_blocks(K kernel, size_t lds, int ncells)
 {
-    hipLaunchKernelGGL((count_kernel<DIM, EXCL>), dim3(blocks), dim3(kBlock), 0, s, in, g, counts);
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                  ? prop.multiProcessorCount
+                  : 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    long long want = (ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long long cap = (long long)cus * per_cu;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    return (int)((want + 7) / 8 * 8);
+}
+
+template <int DIM, int EXCL>
+void launch_count_t(const PairIn& in, const PairGeom& g, int32_t* counts, hipStream_t s)
+{
+    auto k = count_kernel<DIM, EXCL>;
+    const int blocks = resident_blocks(k, 0, g.ncells);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), 0, s, in, g, counts);
 }
 
 template <int DIM, int EXCL>
 void launch_fill_t(const PairIn& in, const PairGeom& g, const FillOut& o, bool nl, bool hist,
-                   int blocks, hipStream_t s)
+                   hipStream_t s)
 {
     const size_t lds = (hist && o.bins <= kMaxLdsBins) ? sizeof(unsigned) * (size_t)o.bins : 0;
-    if (nl && hist)
-        hipLaunchKernelGGL((fill_kernel<DIM, EXCL, true, true>), dim3(blocks), dim3(kBlock), lds, s,
-                           in, g, o);
-    else if (nl)
-        hipLaunchKernelGGL((fill_kernel<DIM, EXCL, true, false>), dim3(blocks), dim3(kBlock), lds,
-                           s, in, g, o);
-    else
-        hipLaunchKernelGGL((fill_kernel<DIM, EXCL, false, true>), dim3(blocks), dim3(kBlock), lds,
-                           s, in, g, o);
+    auto k = nl ? (hist ? fill_kernel<DIM, EXCL, true, true> : fill_kernel<DIM, EXCL, true, false>)
+                : fill_kernel<DIM, EXCL, false, true>;
+    const int blocks = resident_blocks(k, lds, g.ncells);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), lds, s, in, g, o);
 }
 
 PairIn make_in(const PairArgs& a)
@@ -490,10 +759,10 @@ PairIn make_in(const PairArgs& a)
 
 }  // namespace
 
-void launch_count(const PairArgs& a, int dim, int excl, int blocks, hipStream_t s)
+void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s)
 {
     const PairIn in = make_in(a);
-#define PPA_COUNT(D, E) launch_count_t<D, E>(in, a.geom, a.counts, blocks, s)
+#define PPA_COUNT(D, E) launch_count_t<D, E>(in, a.geom, a.counts, s)
     if (dim == 3) {
         if (excl == 1) PPA_COUNT(3, 1); else if (excl == 2) PPA_COUNT(3, 2); else PPA_COUNT(3, 0);
     } else {
@@ -502,8 +771,7 @@ void launch_count(const PairArgs& a, int dim, int excl, int blocks, hipStream_t 
 #undef PPA_COUNT
 }
 
-void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, int blocks,
-                 hipStream_t s)
+void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s)
 {
     const PairIn in = make_in(a);
     FillOut o;
@@ -516,31 +784,13 @@ void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, int b
     o.bins = hist ? a.bins : 0;
     o.r_min = a.r_min;
     o.inv_dr = a.inv_dr;
-#define PPA_FILL(D, E) launch_fill_t<D, E>(in, a.geom, o, nl, hist, blocks, s)
+#define PPA_FILL(D, E) launch_fill_t<D, E>(in, a.geom, o, nl, hist, s)
     if (dim == 3) {
         if (excl == 1) PPA_FILL(3, 1); else if (excl == 2) PPA_FILL(3, 2); else PPA_FILL(3, 0);
     } else {
         if (excl == 1) PPA_FILL(2, 1); else if (excl == 2) PPA_FILL(2, 2); else PPA_FILL(2, 0);
     }
 #undef PPA_FILL
-}
-
-int pair_grid_blocks(int ncells)
-{
-    static int cached = 0;
-    if (cached == 0) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            hipDeviceProp_t prop;
-            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-        }
-        cached = cus * 4;  // four 256-thread workgroups per CU
-    }
-    // at least one home cell per wavefront, and a multiple of 8 (XCD renumbering)
-    long long want = (ncells + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (want > cached) want = cached;
-    if (want < 1) want = 1;
-    return (int)((want + 7) / 8 * 8);
 }
 
 void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,

@@ -67,7 +67,9 @@ def test_small_uniform_ball_and_rdf(ppa):
     lo, hi, amb = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), s.points, 100, 3.0)
     g = counts.cpu().numpy()
     check_hist(g, lo, hi)
-    assert g.sum() == nl.n_pairs
+    # every listed pair is binned by its reported distance (a pair in the band
+    # at r_max may be listed with a distance that rounds to r_max: not binned)
+    assert g.sum() == int((nl.dist.cpu().numpy() < np.float32(3.0)).sum())
     # the same histogram from the stored list
     g2 = ppa.rdf_from_nlist(nl, 100, 3.0).cpu().numpy()
     np.testing.assert_array_equal(g, g2)
@@ -225,7 +227,8 @@ def test_large_fcc_sampled_rows_and_rdf(ppa):
     n_cert, n_amb = check_rows(nl, _oracle_rows(s, 2.5, rows), rows, 2.5)
     assert n_cert > 60 * len(rows)
     g = counts.cpu().numpy()
-    assert g.sum() == nl.n_pairs
+    assert g.sum() == int((nl.dist.cpu().numpy() < np.float32(2.5)).sum())
+    assert nl.n_pairs - g.sum() < 100
     np.testing.assert_array_equal(g, ppa.rdf_from_nlist(nl, 256, 2.5).cpu().numpy())
     cnt = nl.counts.cpu().numpy()
     assert cnt.sum() == nl.n_pairs
@@ -237,3 +240,18 @@ def test_large_fcc_sampled_rows_and_rdf(ppa):
                                   query_points=q, exclude_ii=False)
     # a query point sits on itself at r = 0, which falls in bin 0 for both
     check_hist(sub, lo, hi)
+
+
+def test_small_cutoff_in_sparse_box_uses_exact_test(ppa):
+    """Cells far larger than r_max (few points, capped cell count): the host
+    rejects the expanded in/out test and the difference form runs."""
+    rng = np.random.default_rng(12)
+    centres = rng.uniform(-25, 25, (40, 3))
+    pts = (centres[:, None, :] + rng.normal(0, 0.3, (40, 10, 3))).reshape(-1, 3).astype(np.float32)
+    s = workloads.System((50.0, 50.0, 50.0), (0.1, 0.0, -0.1), 3, pts)
+    box = _box(s)
+    counts, nl = ppa.rdf_counts(box, pts, 20, 0.5, neighbor_list=True)
+    check_rows(nl, _oracle_all(s, 0.5), range(pts.shape[0]), 0.5)
+    lo, hi, _ = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), pts, 20, 0.5)
+    check_hist(counts.cpu().numpy(), lo, hi)
+    assert nl.n_pairs > 500
