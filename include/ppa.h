@@ -127,17 +127,53 @@ int ppa_rdf_from_nlist(const float* dist, const int64_t* n_pairs_dev, int64_t ca
                        int32_t bins, float r_min, float r_max, uint64_t* counts_hist,
                        hipStream_t stream);
 
+/* Workspace bytes for a k-nearest query (ppa_query_knn) on n points and nq
+ * separate query points (0 when the points query themselves).  Host only.
+ * Returns PPA_EINVAL for k outside [1, 64] and PPA_ERANGE for an r_guard at
+ * or beyond half the smallest perpendicular width. */
+int ppa_knn_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t k, float r_guard,
+                            size_t* bytes);
+
+/* k-nearest query: for every query point q_i, the k points nearest to it
+ * (minimum image), excluding j == i when exclude_ii is set (the paper's
+ * query API with a num_neighbors query argument, "Implementation" and the
+ * Steinhardt example).  Neighbours are ordered by (r^2, j): increasing
+ * distance, ties by point index.
+ *   k in [1, 64].
+ *   r_guard: 0 for none; otherwise only points with r < r_guard qualify and
+ *     a row may hold fewer than k (r_guard must be below half the smallest
+ *     perpendicular width).
+ *   pts, qpts, nq, exclude_ii: as for ppa_query_ball.
+ *   flags: reserved, must be 0.
+ *   offsets [nq + 1] int64 device: CSR row pointer in query order.  Without
+ *     r_guard and with n - 1 >= k every row holds exactly k pairs and
+ *     offsets[i] = k i.
+ *   counts [nq] int32 device or NULL: row lengths.
+ *   point_idx [nq * k] int32 device, dist [nq * k] float32 device or NULL:
+ *     the pairs, row after row (offsets[nq] of them are written).
+ *   n_pairs_dev: int64 device, receives offsets[nq].
+ * Without r_guard a row must reach min(k, number of eligible points); if
+ * that needs a neighbour at or beyond half the smallest perpendicular width
+ * (where the minimum image stops being unique), the device status becomes
+ * PPA_ERANGE and the row is incomplete. */
+int ppa_query_knn(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                  int32_t k, float r_guard, int32_t exclude_ii, int32_t flags, void* ws,
+                  size_t ws_bytes, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                  float* dist, int64_t* n_pairs_dev, hipStream_t stream);
+
 /* Profiling hook: the next ppa_query_ball / ppa_rdf call made by this
  * thread records, on its stream, count_start / count_stop around its
  * row-count kernel and fill_start / fill_stop around its fill kernel (the
- * kernel that writes the list and the histogram), then forgets them.  Any
+ * kernel that writes the list and the histogram; for ppa_query_knn, the two
+ * selection kernels), then forgets them.  Any
  * event may be NULL; the events belong to the caller.  Used to time single
  * kernels inside a longer stream of work. */
 int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,
                      hipEvent_t fill_stop);
 
 /* Waits for the stream and returns the device status of the last call that
- * used this workspace (PPA_OK, PPA_ECAPACITY or PPA_ENONFINITE). */
+ * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE or, for a
+ * k-nearest query, PPA_ERANGE). */
 int ppa_sync_status(const void* ws, hipStream_t stream);
 
 /* Message describing the calling thread's last error. */

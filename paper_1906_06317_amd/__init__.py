@@ -106,6 +106,8 @@ def lib():
             "ppa_query_ball": [BP, P, i64, P, i64, f32, i32, i32, P, sz, P, P, P, P, i64, P, P],
             "ppa_rdf": [BP, P, i64, P, i64, i32, f32, f32, i32, i32, P, sz, P, P, P, P, P, i64, P, P],
             "ppa_rdf_from_nlist": [P, P, i64, i32, f32, f32, P, P],
+            "ppa_knn_workspace_bytes": [BP, i64, i64, i32, f32, ctypes.POINTER(sz)],
+            "ppa_query_knn": [BP, P, i64, P, i64, i32, f32, i32, i32, P, sz, P, P, P, P, P, P],
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
         }
@@ -297,6 +299,52 @@ def rdf_counts(box: Box, points, bins, r_max, r_min=0.0, query_points=None, excl
     nl = _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, True, counts, bins,
                     r_min, neighbor_list, ws, stream, check)
     return (counts, nl) if neighbor_list else counts
+
+
+def knn_workspace_bytes(box: Box, n, nq, k, r_guard=0.0):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_knn_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), int(k),
+                                         float(r_guard), ctypes.byref(out)))
+    return out.value
+
+
+def query_knn(box: Box, points, k, query_points=None, exclude_ii=None, r_guard=0.0,
+              with_dist=True, ws=None, stream=None, check=True) -> NeighborList:
+    """The k nearest points of every query point, rows sorted by (r, j).
+
+    r_guard > 0 keeps only neighbours closer than r_guard (rows may then be
+    shorter than k)."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    ws = ws or default_workspace()
+    need = knn_workspace_bytes(box, n, 0 if q is None else nq, k, r_guard)
+    dev = pts.device
+    if nq == 0:
+        return NeighborList(torch.zeros(1, dtype=torch.int64, device=dev),
+                            torch.zeros(0, dtype=torch.int32, device=dev),
+                            torch.zeros(0, dtype=torch.int32, device=dev),
+                            torch.zeros(0, dtype=torch.float32, device=dev) if with_dist else None,
+                            0)
+    wptr, wlen = ws.get(need)
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    counts = torch.empty(nq, dtype=torch.int32, device=dev)
+    cap = max(nq * int(k), 1)
+    pidx = torch.empty(cap, dtype=torch.int32, device=dev)
+    dist = torch.empty(cap, dtype=torch.float32, device=dev) if with_dist else None
+    npairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().ppa_query_knn(ctypes.byref(box.c()), _ptr(pts), n, _ptr(q), nq, int(k),
+                               float(r_guard), int(bool(exclude_ii)), 0, wptr, wlen,
+                               _ptr(offsets), _ptr(counts), _ptr(pidx), _ptr(dist), _ptr(npairs),
+                               _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    np_ = int(npairs.item())
+    return NeighborList(offsets, counts, pidx[:np_], None if dist is None else dist[:np_], np_)
 
 
 def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream=None):

@@ -318,6 +318,161 @@ int run_pairs(const QueryCall& c)
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// ---------------------------------------------------------------------------
+// k nearest neighbours: plan, workspace and launch sequence.
+// ---------------------------------------------------------------------------
+constexpr double kKnnCellScale = 1.15;  // cell width / expected k-th neighbour distance
+constexpr int kKnnMaxK = 64;
+
+struct KnnPlan {
+    Grid g;
+    bool full;     // every row has exactly k entries: written in place at k i
+    double lim;    // search limit: min(r_guard, half the smallest width)
+    double r_est;  // expected k-th neighbour distance at the points' density
+};
+
+int knn_plan(const BoxPrep& bp, int64_t n, int32_t k, float r_guard, KnnPlan* P)
+{
+    if (k < 1 || k > kKnnMaxK) return set_error(PPA_EINVAL, "k must be in [1, %d]", kKnnMaxK);
+    if (!(isfinite(r_guard) && r_guard >= 0.f))
+        return set_error(PPA_EINVAL, "r_guard must be finite and >= 0");
+    int rc;
+    if (r_guard > 0.f && (rc = check_cutoff(bp, r_guard))) return rc;
+    const double half = 0.5 * fmin(bp.width[0], fmin(bp.width[1], bp.width[2]));
+    // two images of one point are at least the smallest width apart, so below
+    // half of it (less a margin for rounding) a point appears at most once
+    P->lim = half * (1.0 - 2e-6);
+    if (r_guard > 0.f) P->lim = fmin(P->lim, (double)r_guard);
+    const double vol = bp.M[0][0] * bp.M[1][1] * (bp.dim == 3 ? bp.M[2][2] : 1.0);
+    const double rho = (double)(n > 0 ? n : 1) / vol;
+    const double unit = bp.dim == 3 ? 4.0 / 3.0 * M_PI : M_PI;
+    P->r_est = pow((double)k / (rho * unit), 1.0 / bp.dim);
+    double cell = kKnnCellScale * P->r_est;
+    if (r_guard > 0.f) cell = fmin(cell, (double)r_guard);  // every row then fits in the block
+    cell = fmin(cell, half);
+    make_grid(bp, cell, n, &P->g);
+    P->full = r_guard == 0.f && n - 1 >= k;
+    return PPA_OK;
+}
+
+// Workspace of a k-nearest query: the cell lists, the deferred-query list
+// and, for rows that may be short, rows staged at stride k plus the scan
+// state of their offsets.
+struct KnnSpace {
+    Workspace W;
+    int* deferred;
+    int32_t* st_idx;
+    float* st_dist;
+    size_t bytes;
+};
+
+size_t knn_layout(const KnnPlan& P, int64_t n, int64_t nq_sep, int32_t k, void* base_v,
+                  KnnSpace* S)
+{
+    char* base = (char*)base_v;
+    size_t off = workspace_layout(P.g, n, nq_sep, P.full ? 0 : PPA_WS_NLIST, base_v, &S->W);
+    const int64_t nrow = nq_sep > 0 ? nq_sep : n;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    S->deferred = (int*)take(sizeof(int) * (size_t)(nrow > 0 ? nrow : 1));
+    S->st_idx = nullptr;
+    S->st_dist = nullptr;
+    if (!P.full) {
+        S->st_idx = (int32_t*)take(sizeof(int32_t) * (size_t)nrow * (size_t)k);
+        S->st_dist = (float*)take(sizeof(float) * (size_t)nrow * (size_t)k);
+    }
+    S->bytes = off;
+    return off;
+}
+
+int run_knn(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+            int32_t k, float r_guard, int32_t exclude_ii, int32_t flags, void* ws,
+            size_t ws_bytes, int64_t* offsets, int32_t* counts, int32_t* point_idx, float* dist,
+            int64_t* n_pairs_dev, hipStream_t s)
+{
+    if (!pts && n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (n > 0x7fffffffLL || nq > 0x7fffffffLL || (int64_t)k * (nq > n ? nq : n) > (1LL << 40))
+        return set_error(PPA_EINVAL, "point counts are limited to 2^31 - 1");
+    if (!qpts && nq != n) return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    if (!offsets || !n_pairs_dev || (!point_idx && nq > 0))
+        return set_error(PPA_EINVAL, "offsets, point_idx and n_pairs_dev are required");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    KnnPlan P;
+    if ((rc = knn_plan(bp, n, k, r_guard, &P))) return rc;
+    const int64_t nq_sep = qpts ? nq : 0;
+    KnnSpace S{};
+    const size_t need = knn_layout(P, n, nq_sep, k, nullptr, &S);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    knn_layout(P, n, nq_sep, k, ws, &S);
+    Workspace& W = S.W;
+    const Grid& g = P.g;
+
+    launch_zero(W, g, qpts != nullptr, nullptr, 0, s);  // also clears the deferred counter
+    launch_build_cells(pts, W.pts, bp, g, W.status, s);
+    if (qpts) launch_build_cells(qpts, W.qry, bp, g, W.status, s);
+
+    KnnArgs A{};
+    A.cand = W.pts.local;
+    A.cand_start = W.pts.cell_start;
+    A.qsorted = W.qry.local;
+    A.q_start = W.qry.cell_start;
+    A.q_cell_of = W.qry.cell_of;
+    for (int d = 0; d < 3; ++d) A.geom.n[d] = g.n[d];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    KnnGeom& K = A.knn;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            K.minv[r][c] = (float)bp.Minv[r][c];
+            K.M[r][c] = bp.M[r][c];
+        }
+    for (int d = 0; d < 3; ++d) {
+        K.nf[d] = (float)g.n[d];
+        K.cellw[d] = (float)(bp.width[d] / g.n[d]);
+    }
+    if (bp.dim == 2) K.cellw[2] = INFINITY;
+    {
+        double wmin = INFINITY;
+        for (int d = 0; d < bp.dim; ++d) wmin = fmin(wmin, bp.width[d] / g.n[d]);
+        K.smax = (int)ceil(P.lim / wmin) + 2;
+    }
+    K.lim2 = (float)(P.lim * P.lim);
+    K.t0 = (float)fmin(1.44 * P.r_est * P.r_est, P.lim * P.lim);
+    K.guard = r_guard > 0.f ? 1 : 0;
+    K.excl = exclude_ii ? 1 : 0;
+    K.k = k;
+    K.n_points = (int)n;
+    A.row_len = P.full ? counts : (counts ? counts : W.qry_row_counts);
+    A.out_idx = P.full ? point_idx : S.st_idx;
+    A.out_dist = P.full ? dist : (dist ? S.st_dist : nullptr);
+    A.deferred = S.deferred;
+    A.n_deferred = W.counters;
+    A.status = W.status;
+
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], s);
+    if (nq > 0) launch_knn(A, bp.dim, s);
+    record(pe.ev[3], s);
+    if (P.full) {
+        launch_knn_offsets(offsets, nq, k, n_pairs_dev, s);
+    } else {
+        launch_scan_i64_total(A.row_len, offsets, nq, W.row_scan_flags, W.row_scan_ticket,
+                              (unsigned long long*)n_pairs_dev, s);
+        launch_knn_pack(nq, k, A.row_len, offsets, S.st_idx, S.st_dist, point_idx, dist, s);
+    }
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -407,6 +562,30 @@ int ppa_rdf_from_nlist(const float* dist, const int64_t* n_pairs_dev, int64_t ca
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+int ppa_knn_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t k, float r_guard,
+                            size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    KnnPlan P;
+    if ((rc = knn_plan(bp, n, k, r_guard, &P))) return rc;
+    KnnSpace S{};
+    *bytes = knn_layout(P, n, nq, k, nullptr, &S);
+    return PPA_OK;
+}
+
+int ppa_query_knn(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                  int32_t k, float r_guard, int32_t exclude_ii, int32_t flags, void* ws,
+                  size_t ws_bytes, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                  float* dist, int64_t* n_pairs_dev, hipStream_t stream)
+{
+    return run_knn(box, pts, n, qpts, nq, k, r_guard, exclude_ii, flags, ws, ws_bytes, offsets,
+                   counts, point_idx, dist, n_pairs_dev, stream);
+}
+
 int ppa_sync_status(const void* ws, hipStream_t stream)
 {
     if (!ws) return set_error(PPA_EINVAL, "workspace is NULL");
@@ -417,6 +596,10 @@ int ppa_sync_status(const void* ws, hipStream_t stream)
     if (rc) return rc;
     if (st & kStatusNonFinite) return set_error(PPA_ENONFINITE, "input has a non-finite coordinate");
     if (st & kStatusCapacity) return set_error(PPA_ECAPACITY, "more pairs than the output capacity");
+    if (st & kStatusRange)
+        return set_error(PPA_ERANGE,
+                         "a k-nearest row needs a neighbour at or beyond half the smallest "
+                         "perpendicular box width");
     return PPA_OK;
 }
 

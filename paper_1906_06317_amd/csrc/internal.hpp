@@ -18,6 +18,7 @@ constexpr int kMaxLdsBins = 4096;       // histograms up to this size live in LD
 // Device status bits (the status word in the workspace).
 constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusCapacity = 2u;
+constexpr unsigned kStatusRange = 4u;   // a k-nearest row reaches half the box width
 
 // Box prepared on the host in float64.
 struct BoxPrep {
@@ -72,7 +73,7 @@ struct Workspace {
     size_t bytes;
 };
 
-// Host helpers (host.cpp).
+// Host helpers (api.hip).
 int prepare_box(const ppa_box* box, BoxPrep* out);
 int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g);
 size_t workspace_layout(const Grid& g, int64_t n, int64_t nq, int32_t flags, void* base,
@@ -124,6 +125,44 @@ struct PairArgs {
 // entry), 2 separate query points (drop j == i by index).
 void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s);
 void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s);
+
+// k nearest neighbours (knn.hip).
+struct KnnGeom {
+    float minv[3][3];   // M^-1 in float32 (upper triangular)
+    float nf[3];        // cells per axis
+    float cellw[3];     // perpendicular cell widths d_k / n_k
+    double M[3][3];     // lattice vectors, for the offsets of far shells
+    float lim2;         // squared search limit: min(r_guard, half the smallest width)^2
+    float t0;           // first threshold guess (r^2)
+    int guard;          // 1: r_guard limits the rows (rows may be short)
+    int excl;           // 1: drop the point whose index is the query's
+    int k;
+    int n_points;
+    int smax;           // last shell of the far search (its radius passes the limit)
+};
+
+struct KnnArgs {
+    const float4* cand;       // points sorted by cell
+    const int* cand_start;    // [ncells + 1]
+    const float4* qsorted;    // query points sorted by cell
+    const int* q_start;       // [ncells + 1]
+    const int* q_cell_of;     // [nq] home cell of each query (by query index)
+    PairGeom geom;
+    KnnGeom knn;
+    int32_t* out_idx;         // rows at stride k
+    float* out_dist;          // rows at stride k, or NULL
+    int32_t* row_len;         // [nq] or NULL
+    int* deferred;            // [nq] sorted positions of queries for the shell search
+    unsigned long long* n_deferred;
+    unsigned* status;
+};
+
+void launch_knn(const KnnArgs& a, int dim, hipStream_t s);
+void launch_knn_offsets(int64_t* offsets, int64_t nq, int k, int64_t* n_pairs, hipStream_t s);
+void launch_knn_pack(int64_t nq, int k, const int32_t* row_len, const int64_t* offsets,
+                     const int32_t* st_idx, const float* st_dist, int32_t* point_idx, float* dist,
+                     hipStream_t s);
+
 void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,
                            float r_min, float inv_dr, unsigned long long* hist, hipStream_t s);
 

@@ -28,228 +28,17 @@
 // histogram bin and coalesced stores for 64 hits per instruction.  The RDF
 // alone (no list) needs only the fill pass.  Stencils with more candidates
 // than the register slots hold are processed in chunks, writing directly.
-#include "internal.hpp"
+#include "pair_common.hpp"
 
 namespace ppa {
 
 namespace {
 
-constexpr float kFar = 1.0e18f;
+using namespace pair;
+
 constexpr int kHitCap = 384;  // hits buffered per wavefront between flushes
 constexpr int kRows = 64;     // rows buffered per wavefront
-constexpr int kChunkSlots = 8;  // slots per chunk of an oversized stencil
 constexpr int kFillSlots = 10;  // register slots of the fill pass (it needs more registers)
-
-__device__ __forceinline__ unsigned lane_prefix(unsigned long long mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ float uniformf(float v)
-{
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-__device__ __forceinline__ int lane_of(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
-
-__device__ __forceinline__ float lane_off(float v, int t)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
-}
-
-__device__ __forceinline__ long long lane_of64(long long v, int t)
-{
-    const unsigned lo = (unsigned)lane_of((int)(unsigned)v, t);
-    const unsigned hi = (unsigned)lane_of((int)(v >> 32), t);
-    return (long long)(((unsigned long long)hi << 32) | lo);
-}
-
-// Square root by the hardware instruction (within 1 ulp).
-__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int DIM>
-__device__ __forceinline__ float dist2(float dx, float dy, float dz)
-{
-    return DIM == 3 ? fmaf(dz, dz, fmaf(dy, dy, dx * dx)) : fmaf(dy, dy, dx * dx);
-}
-
-// Inputs shared by the pair kernels.
-struct PairIn {
-    const float4* __restrict__ cand;     // points sorted by cell (local xyz, index bits)
-    const int* __restrict__ cand_start;  // [ncells + 1]
-    const float4* __restrict__ qs;       // query points sorted by cell
-    const int* __restrict__ q_start;     // [ncells + 1]
-};
-
-struct StencilLds {
-    int pre[32];
-    int start[32];
-};
-
-// Home cells of this wavefront: [t0, t1).
-__device__ __forceinline__ void wave_tiles(int ncells, int wv, int& t0, int& t1)
-{
-    const int G = gridDim.x;
-    const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-    const long long gw = (long long)lb * kWavesPerBlock + wv;
-    const long long nw = (long long)G * kWavesPerBlock;
-    t0 = uniform((int)(gw * ncells / nw));
-    t1 = uniform((int)((gw + 1) * ncells / nw));
-}
-
-// Stencil slot -> offset code d = (dx+1) + 3 (dy+1) + 9 (dz+1): the home
-// cell (centre code) is slot 0 and takes the place of code 0.
-__device__ __forceinline__ int stencil_code(int s, int nsten)
-{
-    const int centre = nsten / 2;
-    return s == 0 ? centre : (s == centre ? 0 : s);
-}
-
-// Stencil of home cell `tile`: per-offset starts and prefix counts in LDS;
-// returns the candidate count C (uniform).
-template <int DIM>
-__device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int tile, int lane,
-                                       StencilLds& S)
-{
-    const int cx = tile % G.n[0];
-    const int rest = tile / G.n[0];
-    const int cy = rest % G.n[1];
-    const int cz = rest / G.n[1];
-    int cnt = 0, st = 0;
-    if (lane < G.nsten) {
-        // slot 0 is the home cell itself (offset code 13 in 3D, 4 in 2D)
-        const int code = stencil_code(lane, G.nsten);
-        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = DIM == 3 ? code / 9 - 1 : 0;
-        int x = cx + dx, y = cy + dy, z = cz + dz;
-        x += x < 0 ? G.n[0] : 0;
-        x -= x >= G.n[0] ? G.n[0] : 0;
-        y += y < 0 ? G.n[1] : 0;
-        y -= y >= G.n[1] ? G.n[1] : 0;
-        z += z < 0 ? G.n[2] : 0;
-        z -= z >= G.n[2] ? G.n[2] : 0;
-        const int nc = (z * G.n[1] + y) * G.n[0] + x;
-        st = in.cand_start[nc];
-        cnt = in.cand_start[nc + 1] - st;
-    }
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-    }
-    if (lane < G.nsten) {
-        S.pre[lane + 1] = incl;
-        S.start[lane] = st;
-    }
-    if (lane == 0) S.pre[0] = 0;
-    wave_sync();
-    return uniform(__shfl(incl, G.nsten - 1));
-}
-
-// Candidate at flat stencil index k, relative to the home cell's centre.
-template <int DIM>
-__device__ __forceinline__ void fetch(const PairIn& in, const PairGeom& G, const StencilLds& S,
-                                      const float4* off, int k, float& x, float& y, float& z,
-                                      int& id)
-{
-    int j = 0;
-#pragma unroll
-    for (int step = 16; step > 0; step >>= 1)
-        if (j + step < G.nsten && S.pre[j + step] <= k) j += step;
-    const float4 v = in.cand[S.start[j] + (k - S.pre[j])];
-    const float4 o = off[j];
-    x = v.x + o.x;
-    y = v.y + o.y;
-    z = DIM == 3 ? v.z + o.z : 0.f;
-    id = __float_as_int(v.w);
-}
-
-// One query point in scalar registers, with the constants of both tests.
-struct Query {
-    float x, y, z;
-    float m2x, m2y, m2z;  // -2 q
-    float thr;            // r_max^2 - |q|^2
-    int id;
-};
-
-template <int DIM>
-__device__ __forceinline__ Query make_query(float x, float y, float z, int id, float r2max)
-{
-    Query q;
-    q.x = x;
-    q.y = y;
-    q.z = DIM == 3 ? z : 0.f;
-    q.m2x = -2.f * x;
-    q.m2y = -2.f * y;
-    q.m2z = -2.f * q.z;
-    q.thr = uniformf(r2max - dist2<DIM>(x, y, q.z));
-    q.id = id;
-    return q;
-}
-
-// The candidates of one home cell in NS register slots (entries past the
-// end are far away, so they never hit).
-template <int DIM, int NS>
-struct Slots {
-    float x[NS > 0 ? NS : 1], y[NS > 0 ? NS : 1], z[NS > 0 ? NS : 1];
-    float cc[NS > 0 ? NS : 1];  // |c|^2
-    int id[NS > 0 ? NS : 1];
-
-    __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
-                                         const float4* off, int k0, int C, int lane)
-    {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            x[s] = y[s] = z[s] = kFar;
-            id[s] = -1;
-            const int k = k0 + s * kWave + lane;
-            if (k < C) fetch<DIM>(in, G, S, off, k, x[s], y[s], z[s], id[s]);
-            cc[s] = dist2<DIM>(x[s], y[s], z[s]);
-        }
-    }
-    // the in/out test of slot s against q; identical in both passes
-    template <bool DOT>
-    __device__ __forceinline__ bool hit(int s, const Query& q, float r2max) const
-    {
-        if (DOT) {
-            float t = fmaf(x[s], q.m2x, cc[s]);
-            t = fmaf(y[s], q.m2y, t);
-            if (DIM == 3) t = fmaf(z[s], q.m2z, t);
-            return t < q.thr;
-        }
-        return dist2<DIM>(x[s] - q.x, y[s] - q.y, z[s] - q.z) < r2max;
-    }
-};
-
-// Query points of a tile, 64 at a time, one per lane.
-struct QueryChunk {
-    float4 q;
-    int n;
-
-    __device__ __forceinline__ void load(const PairIn& in, int first, int count, int lane)
-    {
-        n = uniform(min(kWave, count));
-        q = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane < n) q = in.qs[first + lane];
-    }
-    template <int DIM>
-    __device__ __forceinline__ Query get(int t, float r2max) const
-    {
-        return make_query<DIM>(lane_off(q.x, t), lane_off(q.y, t), lane_off(q.z, t),
-                               lane_of(__float_as_int(q.w), t), r2max);
-    }
-    __device__ __forceinline__ int my_id() const { return __float_as_int(q.w); }
-};
 
 // ---------------------------------------------------------------------------
 // Pass 1: row lengths.
@@ -702,30 +491,6 @@ __global__ void __launch_bounds__(256) hist_from_dist_kernel(const float* __rest
             const unsigned v = s_hist[b];
             if (v) atomicAdd(&hist[b], (unsigned long long)v);
         }
-}
-
-// Workgroups for a persistent launch of `kernel`: as many as fit on the
-// device at once, at least one home cell per wavefront, a multiple of 8.
-template <typename K>
-int resident_blocks(K kernel, size_t lds, int ncells)
-{
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    long long want = (ncells + kWavesPerBlock - 1) / kWavesPerBlock;
-    const long long cap = (long long)cus * per_cu;
-    if (want > cap) want = cap;
-    if (want < 1) want = 1;
-    return (int)((want + 7) / 8 * 8);
 }
 
 template <int DIM, int EXCL>

@@ -58,3 +58,58 @@ def check_hist(gpu_counts, lo, hi):
     hi = hi.astype(np.int64)
     bad = np.nonzero((g < lo) | (g > hi))[0]
     assert bad.size == 0, f"bins outside [lo, hi]: {bad[:10]} gpu={g[bad[:10]]} lo={lo[bad[:10]]} hi={hi[bad[:10]]}"
+
+
+def check_knn_rows(nl, o_idx, o_r2, o_len, rows, k, r_guard=0.0, dist_atol=4e-6, dist_rtol=2e-6):
+    """Checks GPU k-nearest rows against oracle rows.
+
+    o_idx/o_r2/o_len: oracle output for exactly `rows` (row t of the oracle is
+    query rows[t]), k + extra entries each in (r^2, j) order; with r_guard the
+    oracle must have been run with the guard widened by the band.  A neighbour
+    is ambiguous when its r^2 lies within REL of the k-th r^2 (or of
+    r_guard^2).  Returns (n_certain, n_ambiguous)."""
+    g = gpu_rows(nl, rows)
+    m = o_idx.shape[1]
+    g2 = r_guard * r_guard
+    n_cert = n_amb = 0
+    for t, q in enumerate(rows):
+        ln = int(o_len[t])
+        oi = o_idx[t, :ln]
+        orr = o_r2[t, :ln]
+        gi, gd = g[int(q)]
+        assert len(np.unique(gi)) == len(gi), f"duplicate neighbours in row {q}"
+        in_guard = np.ones(ln, bool) if r_guard <= 0 else orr < g2 * (1 + REL)
+        sure_guard = np.ones(ln, bool) if r_guard <= 0 else orr < g2 * (1 - REL)
+        if len(gi) == k:
+            r2k = orr[k - 1] if ln >= k else np.inf
+            allowed = (orr <= r2k * (1 + REL)) & in_guard
+            certain = (orr < r2k * (1 - REL)) & sure_guard
+            # the oracle's extra entries must reach past the band
+            assert ln < m or orr[-1] > r2k * (1 + REL), f"row {q}: oracle needs more extra entries"
+        else:
+            assert len(gi) < k
+            allowed = in_guard
+            certain = sure_guard
+            assert ln < m or (r_guard > 0 and orr[-1] >= g2 * (1 + REL)), f"row {q}: short row"
+            assert int(certain.sum()) <= len(gi) <= int(allowed.sum()), (
+                f"row {q}: {len(gi)} neighbours, oracle certain {certain.sum()} allowed {allowed.sum()}")
+        gs = set(gi.tolist())
+        cs = set(oi[certain].tolist())
+        al = set(oi[allowed].tolist())
+        missing = cs - gs
+        extra = gs - al
+        assert not missing and not extra, (
+            f"row {q}: missing {sorted(missing)[:10]} extra {sorted(extra)[:10]}")
+        if len(gi):
+            ref = dict(zip(oi.tolist(), orr.tolist()))
+            r2 = np.array([ref[j] for j in gi.tolist()])
+            if gd is not None:
+                r = np.sqrt(r2)
+                err = np.abs(gd.astype(np.float64) - r)
+                assert np.all(err <= dist_atol + dist_rtol * r), f"row {q}: max dist error {err.max()}"
+                assert np.all(np.diff(gd) >= 0), f"row {q}: distances not sorted"
+            # sorted by r^2 up to near-ties
+            assert np.all(r2[:-1] <= r2[1:] * (1 + 2 * REL) + 1e-12), f"row {q}: order"
+        n_cert += len(cs)
+        n_amb += len(al) - len(cs)
+    return n_cert, n_amb

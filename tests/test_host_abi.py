@@ -141,3 +141,43 @@ def test_binding_has_no_cpu_fallback():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "liboracle" not in src, f
+
+
+def test_knn_workspace_and_argument_errors():
+    L = ppa.lib()
+    box = ppa.Box.cube(10.0)
+    full = ppa.knn_workspace_bytes(box, 1000, 0, 12)
+    assert full > 0
+    # rows that may be short (a guard, or fewer points than k) are staged
+    assert ppa.knn_workspace_bytes(box, 1000, 0, 12, r_guard=2.0) > full
+    assert ppa.knn_workspace_bytes(box, 5, 0, 12) > ppa.knn_workspace_bytes(box, 5, 0, 4)
+    for k in (0, 65, -3):
+        with pytest.raises(ppa.PPAError) as e:
+            ppa.knn_workspace_bytes(box, 1000, 0, k)
+        assert e.value.code == ppa.PPA_EINVAL
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.knn_workspace_bytes(box, 1000, 0, 12, r_guard=5.0)
+    assert e.value.code == ppa.PPA_ERANGE
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.knn_workspace_bytes(box, 1000, 0, 12, r_guard=-1.0)
+    assert e.value.code == ppa.PPA_EINVAL
+    cb = box.c()
+
+    def call(k=12, n=10, nq=10, guard=0.0, flags=0, ws=256, ws_bytes=1 << 40, offsets=8, pidx=8,
+             npairs=8):
+        return L.ppa_query_knn(ctypes.byref(cb), ctypes.c_void_p(64), n, None, nq, k, guard, 1,
+                               flags, ctypes.c_void_p(ws) if ws else None, ws_bytes,
+                               ctypes.c_void_p(offsets) if offsets else None, None,
+                               ctypes.c_void_p(pidx) if pidx else None, None,
+                               ctypes.c_void_p(npairs) if npairs else None, None)
+    assert call(k=0) == ppa.PPA_EINVAL
+    assert call(k=100) == ppa.PPA_EINVAL
+    assert call(nq=5) == ppa.PPA_EINVAL
+    assert call(flags=2) == ppa.PPA_EINVAL
+    assert call(offsets=0) == ppa.PPA_EINVAL
+    assert call(pidx=0) == ppa.PPA_EINVAL
+    assert call(npairs=0) == ppa.PPA_EINVAL
+    assert call(guard=float("nan")) == ppa.PPA_EINVAL
+    assert call(guard=7.0) == ppa.PPA_ERANGE
+    assert call(ws=0) == ppa.PPA_EWORKSPACE
+    assert call(ws_bytes=64) == ppa.PPA_EWORKSPACE
