@@ -161,11 +161,41 @@ int ppa_query_knn(const ppa_box* box, const float* pts, int64_t n, const float* 
                   size_t ws_bytes, int64_t* offsets, int32_t* counts, int32_t* point_idx,
                   float* dist, int64_t* n_pairs_dev, hipStream_t stream);
 
+/* Workspace bytes for ppa_pmft2d with these arguments (nq: separate query
+ * points, 0 when the points query themselves).  Queries the current device
+ * (its compute-unit count and LDS size set the launch) but does no device
+ * work.  Same error codes as ppa_pmft2d's host checks. */
+int ppa_pmft2d_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx, int32_t nby,
+                               float x_max, float y_max, float r_max, size_t* bytes);
+
+/* 2D PMFT histogram (the paper's PMFT section, in 2D: positions of the
+ * other particles seen from each particle's own frame).  For every ball pair
+ * (i, j) with |p_j - q_i| < r_max (minimum image), excluding j == i when
+ * exclude_ii is set, the bond d = p_j - q_i is rotated by -theta_i:
+ *     x' =  cos(theta_i) d_x + sin(theta_i) d_y,
+ *     y' = -sin(theta_i) d_x + cos(theta_i) d_y,
+ * and counted in bin (ix, iy) = (floor((x' + x_max) / dx),
+ * floor((y' + y_max) / dy)), dx = 2 x_max / nbx, dy = 2 y_max / nby, when
+ * both lie in range.  counts[ix * nby + iy] += the count (uint32, device,
+ * accumulated; it wraps past 2^32).
+ *   box: dim must be 2 (PPA_EINVAL otherwise).
+ *   pts [n x 3], qpts [nq x 3] or NULL, exclude_ii: as for ppa_query_ball.
+ *   angles [nq] float32 device: orientation theta of each query point in
+ *     radians (of pts when qpts is NULL).
+ *   nbx, nby >= 1; x_max, y_max > 0; r_max below half the smallest width.
+ *   flags: reserved, must be 0.
+ * The PMFT itself is minus the log of the normalised counts (host side). */
+int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
+               const float* angles, int64_t nq, int32_t nbx, int32_t nby, float x_max,
+               float y_max, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+               size_t ws_bytes, uint32_t* counts, hipStream_t stream);
+
 /* Profiling hook: the next ppa_query_ball / ppa_rdf call made by this
  * thread records, on its stream, count_start / count_stop around its
  * row-count kernel and fill_start / fill_stop around its fill kernel (the
  * kernel that writes the list and the histogram; for ppa_query_knn, the two
- * selection kernels), then forgets them.  Any
+ * selection kernels; for ppa_pmft2d, the binning and the sum of the
+ * per-workgroup histograms), then forgets them.  Any
  * event may be NULL; the events belong to the caller.  Used to time single
  * kernels inside a longer stream of work. */
 int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,

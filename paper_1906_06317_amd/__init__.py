@@ -108,6 +108,9 @@ def lib():
             "ppa_rdf_from_nlist": [P, P, i64, i32, f32, f32, P, P],
             "ppa_knn_workspace_bytes": [BP, i64, i64, i32, f32, ctypes.POINTER(sz)],
             "ppa_query_knn": [BP, P, i64, P, i64, i32, f32, i32, i32, P, sz, P, P, P, P, P, P],
+            "ppa_pmft2d_workspace_bytes": [BP, i64, i64, i32, i32, f32, f32, f32,
+                                           ctypes.POINTER(sz)],
+            "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
         }
@@ -345,6 +348,59 @@ def query_knn(box: Box, points, k, query_points=None, exclude_ii=None, r_guard=0
         _check(ws.status(stream))
     np_ = int(npairs.item())
     return NeighborList(offsets, counts, pidx[:np_], None if dist is None else dist[:np_], np_)
+
+
+def pmft2d_workspace_bytes(box: Box, n, nq, nbx, nby, x_max, y_max, r_max):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_pmft2d_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), int(nbx),
+                                            int(nby), float(x_max), float(y_max), float(r_max),
+                                            ctypes.byref(out)))
+    return out.value
+
+
+def pmft2d_counts(box: Box, points, angles, nbx, nby, x_max, y_max, r_max, query_points=None,
+                  exclude_ii=None, counts=None, ws=None, stream=None, check=True):
+    """2D PMFT bond histogram, uint32 [nbx, nby] (accumulated into `counts`).
+
+    `angles` are the orientations of the query points (of `points` when
+    query_points is None), in radians."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    th = angles
+    if not isinstance(th, torch.Tensor):
+        th = torch.as_tensor(np.ascontiguousarray(th, dtype=np.float32))
+    th = th.to(device=pts.device, dtype=torch.float32).contiguous().reshape(-1)
+    if th.shape[0] != nq:
+        raise ValueError("one orientation per query point is required")
+    if counts is None:
+        counts = torch.zeros((int(nbx), int(nby)), dtype=torch.uint32, device=pts.device)
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(pmft2d_workspace_bytes(box, n, 0 if q is None else nq, nbx, nby, x_max,
+                                               y_max, r_max))
+    _check(lib().ppa_pmft2d(ctypes.byref(box.c()), _ptr(pts), n, _ptr(q), _ptr(th), nq, int(nbx),
+                            int(nby), float(x_max), float(y_max), float(r_max),
+                            int(bool(exclude_ii)), 0, wptr, wlen, _ptr(counts), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return counts
+
+
+def normalize_pmft2d(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
+    """(pair correlation, PMFT) from 2D PMFT counts, float64 on the host:
+    pcf = counts / (n_frames N_q rho dx dy) with rho = N_p / area, and
+    PMFT = -ln(pcf) (+inf where a bin is empty)."""
+    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
+    nbx, nby = c.shape
+    dxdy = (2.0 * x_max / nbx) * (2.0 * y_max / nby)
+    pcf = c / (n_frames * n_query * (n_points / area) * dxdy)
+    with np.errstate(divide="ignore"):
+        pmft = -np.log(pcf)
+    return pcf, pmft
 
 
 def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream=None):

@@ -473,6 +473,126 @@ int run_knn(const ppa_box* box, const float* pts, int64_t n, const float* qpts, 
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// ---------------------------------------------------------------------------
+// 2D PMFT: plan (reachable-bin table, launch shape), workspace, launches.
+// ---------------------------------------------------------------------------
+struct PmftPlan {
+    Grid g;
+    PmftTable table;
+    int words;   // LDS histogram words (0: global atomics)
+    int blocks;
+};
+
+int pmft_plan(const BoxPrep& bp, int64_t n, int32_t nbx, int32_t nby, float x_max, float y_max,
+              float r_max, PmftPlan* P)
+{
+    if (bp.dim != 2) return set_error(PPA_EINVAL, "the 2D PMFT needs a 2D box");
+    if (nbx < 1 || nby < 1 || (int64_t)nbx * nby > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "bad bin counts %d x %d", nbx, nby);
+    if (!(isfinite(x_max) && x_max > 0.f && isfinite(y_max) && y_max > 0.f))
+        return set_error(PPA_EINVAL, "x_max and y_max must be finite and positive");
+    if (!(isfinite(r_max) && r_max > 0.f)) return set_error(PPA_EINVAL, "r_max must be positive");
+    int rc;
+    if ((rc = check_cutoff(bp, r_max))) return rc;
+    make_grid(bp, r_max, n, &P->g);
+    // bins a bond shorter than r_max can reach: per row ix, the iy range
+    // covering |y| < sqrt(r_max^2 - min|x|^2), widened by a bin each side
+    P->words = 0;
+    if (nbx <= kPmftMaxRows) {
+        const double dx = 2.0 * x_max / nbx, dy = 2.0 * y_max / nby, r = r_max;
+        int base = 0;
+        for (int ix = 0; ix < nbx; ++ix) {
+            const double x0 = -(double)x_max + ix * dx, x1 = x0 + dx;
+            const double mx = (x0 <= 0.0 && x1 >= 0.0) ? 0.0 : fmin(fabs(x0), fabs(x1));
+            int lo = 0, hi = 0;
+            if (mx < r * (1.0 + 1e-4)) {
+                const double ym = sqrt(fmax(0.0, r * r - mx * mx)) * (1.0 + 1e-4) + 1e-6 * r;
+                lo = (int)fmax(0.0, floor((y_max - ym) / dy) - 1.0);
+                hi = (int)fmin((double)nby, floor((y_max + ym) / dy) + 2.0);
+                if (hi < lo) hi = lo;
+            }
+            P->table.lo[ix] = lo;
+            P->table.base[ix] = base;
+            base += hi - lo;
+        }
+        P->table.base[nbx] = base;
+        if ((size_t)base * sizeof(unsigned) <= pmft_lds_limit()) P->words = base;
+    }
+    P->blocks = pmft_workgroups(P->words);
+    return PPA_OK;
+}
+
+size_t pmft_layout(const PmftPlan& P, int64_t n, int64_t nq_sep, void* base_v, Workspace* W,
+                   unsigned** partial)
+{
+    char* base = (char*)base_v;
+    size_t off = workspace_layout(P.g, n, nq_sep, 0, base_v, W);
+    *partial = base ? (unsigned*)(base + off) : nullptr;
+    off += sizeof(unsigned) * (size_t)P.blocks * (size_t)P.words;
+    return (off + 255) & ~(size_t)255;
+}
+
+int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
+             const float* angles, int64_t nq, int32_t nbx, int32_t nby, float x_max, float y_max,
+             float r_max, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
+             uint32_t* counts, hipStream_t s)
+{
+    if (!pts && n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (n > 0x7fffffffLL || nq > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "point counts are limited to 2^31 - 1");
+    if (!qpts && nq != n) return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (!angles && nq > 0) return set_error(PPA_EINVAL, "orientations pointer is NULL");
+    if (!counts) return set_error(PPA_EINVAL, "counts pointer is NULL");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    PmftPlan P;
+    if ((rc = pmft_plan(bp, n, nbx, nby, x_max, y_max, r_max, &P))) return rc;
+    const int64_t nq_sep = qpts ? nq : 0;
+    Workspace W{};
+    unsigned* partial = nullptr;
+    const size_t need = pmft_layout(P, n, nq_sep, nullptr, &W, &partial);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    pmft_layout(P, n, nq_sep, ws, &W, &partial);
+    if (nq == 0) return PPA_OK;
+    const Grid& g = P.g;
+    launch_zero(W, g, qpts != nullptr, nullptr, 0, s);
+    launch_build_cells(pts, W.pts, bp, g, W.status, s);
+    if (qpts) launch_build_cells(qpts, W.qry, bp, g, W.status, s);
+
+    PmftArgs A{};
+    A.cand = W.pts.local;
+    A.cand_start = W.pts.cell_start;
+    A.qsorted = W.qry.local;
+    A.q_start = W.qry.cell_start;
+    A.angles = angles;
+    for (int d = 0; d < 3; ++d) A.geom.n[d] = g.n[d];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    A.geom.r2max = r_max * r_max;
+    A.excl = exclude_ii ? 1 : 0;
+    A.nbx = nbx;
+    A.nby = nby;
+    A.x_max = x_max;
+    A.y_max = y_max;
+    A.inv_dx = (float)((double)nbx / (2.0 * x_max));
+    A.inv_dy = (float)((double)nby / (2.0 * y_max));
+    A.words = P.words;
+    A.partial = partial;
+    A.counts = counts;
+    A.table = P.table;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], s);
+    launch_pmft(A, P.blocks, s);
+    record(pe.ev[3], s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -584,6 +704,31 @@ int ppa_query_knn(const ppa_box* box, const float* pts, int64_t n, const float* 
 {
     return run_knn(box, pts, n, qpts, nq, k, r_guard, exclude_ii, flags, ws, ws_bytes, offsets,
                    counts, point_idx, dist, n_pairs_dev, stream);
+}
+
+int ppa_pmft2d_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx, int32_t nby,
+                               float x_max, float y_max, float r_max, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    PmftPlan P;
+    if ((rc = pmft_plan(bp, n, nbx, nby, x_max, y_max, r_max, &P))) return rc;
+    Workspace W{};
+    unsigned* partial = nullptr;
+    *bytes = pmft_layout(P, n, nq, nullptr, &W, &partial);
+    return PPA_OK;
+}
+
+int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
+               const float* angles, int64_t nq, int32_t nbx, int32_t nby, float x_max,
+               float y_max, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+               size_t ws_bytes, uint32_t* counts, hipStream_t stream)
+{
+    return run_pmft(box, pts, n, qpts, angles, nq, nbx, nby, x_max, y_max, r_max, exclude_ii,
+                    flags, ws, ws_bytes, counts, stream);
 }
 
 int ppa_sync_status(const void* ws, hipStream_t stream)

@@ -163,6 +163,39 @@ void launch_knn_pack(int64_t nq, int k, const int32_t* row_len, const int64_t* o
                      const int32_t* st_idx, const float* st_dist, int32_t* point_idx, float* dist,
                      hipStream_t s);
 
+// 2D PMFT (pmft.hip).  Bins of the histogram a bond shorter than r_max can
+// reach, row by row: row ix keeps bins iy in [lo[ix], lo[ix] + base[ix+1] -
+// base[ix]) at LDS words base[ix] onwards.
+constexpr int kPmftMaxRows = 256;
+
+struct PmftTable {
+    int lo[kPmftMaxRows];
+    int base[kPmftMaxRows + 1];
+};
+
+struct PmftArgs {
+    const float4* cand;       // points sorted by cell
+    const int* cand_start;    // [ncells + 1]
+    const float4* qsorted;    // query points sorted by cell
+    const int* q_start;       // [ncells + 1]
+    const float* angles;      // [nq] orientation of each query point (radians)
+    PairGeom geom;
+    int excl;                 // 1: drop the point whose index is the query's
+    int nbx, nby;
+    float x_max, y_max;
+    float inv_dx, inv_dy;     // bins per unit length
+    int words;                // LDS words of the compacted histogram (0: global atomics)
+    unsigned* partial;        // [gridDim.x][words] per-workgroup histograms
+    unsigned* counts;         // [nbx * nby] accumulated
+    PmftTable table;
+};
+
+// Returns the number of workgroups launched (partials needed), or a negative
+// PPA error when the launch failed.
+int pmft_workgroups(int words);
+size_t pmft_lds_limit();  // bytes of LDS a workgroup may give the histogram
+void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s);
+
 void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,
                            float r_min, float inv_dr, unsigned long long* hist, hipStream_t s);
 

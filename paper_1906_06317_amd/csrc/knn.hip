@@ -80,7 +80,7 @@ __device__ __forceinline__ int expected_len(const KnnGeom& K, int qid)
 }
 
 struct KnnLds {
-    unsigned long long key[kWave];
+    alignas(16) unsigned long long key[kWave];
     StencilLds st;
 };
 
@@ -176,7 +176,9 @@ __device__ __forceinline__ void knn_tile(const KnnArgs& a, const PairIn& in, con
                 defer |= 1ull << t;
                 continue;
             }
-            // compact the candidates under T and rank them
+            // compact the candidates under T (the rest of the buffer holds
+            // keys that sort last) and rank them
+            W.key[lane] = kNoKey;
             int nb = 0;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -186,9 +188,15 @@ __device__ __forceinline__ void knn_tile(const KnnArgs& a, const PairIn& in, con
                 nb += __popcll(m);
             }
             wave_sync();
-            const unsigned long long mine = lane < cnt ? W.key[lane] : kNoKey;
+            const unsigned long long mine = W.key[lane];
             int r = 0;
-            for (int u = 0; u < cnt; ++u) r += W.key[u] < mine ? 1 : 0;
+            // four keys per step: independent LDS reads overlap their latency
+            for (int u = 0; u < cnt; u += 4) {
+                const ulonglong2 a2 = *reinterpret_cast<const ulonglong2*>(&W.key[u]);
+                const ulonglong2 b2 = *reinterpret_cast<const ulonglong2*>(&W.key[u + 2]);
+                r += (a2.x < mine ? 1 : 0) + (a2.y < mine ? 1 : 0) + (b2.x < mine ? 1 : 0) +
+                     (b2.y < mine ? 1 : 0);
+            }
             const int len = state == kRowFull ? k : cnt;
             if (lane < cnt && r < len) {
                 const long long o = (long long)k * qid + r;

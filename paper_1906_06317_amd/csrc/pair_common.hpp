@@ -67,15 +67,23 @@ struct StencilLds {
     int start[32];
 };
 
-// Home cells of this wavefront: [t0, t1).
-__device__ __forceinline__ void wave_tiles(int ncells, int wv, int& t0, int& t1)
+// Home cells of this wavefront: [t0, t1).  Workgroups are renumbered so the
+// workgroups of one XCD (dispatched round-robin over the 8 XCDs) own a
+// contiguous range of cells; the grid is a multiple of 8.
+template <int WPB>
+__device__ __forceinline__ void wave_tiles_n(int ncells, int wv, int& t0, int& t1)
 {
     const int G = gridDim.x;
     const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-    const long long gw = (long long)lb * kWavesPerBlock + wv;
-    const long long nw = (long long)G * kWavesPerBlock;
+    const long long gw = (long long)lb * WPB + wv;
+    const long long nw = (long long)G * WPB;
     t0 = uniform((int)(gw * ncells / nw));
     t1 = uniform((int)((gw + 1) * ncells / nw));
+}
+
+__device__ __forceinline__ void wave_tiles(int ncells, int wv, int& t0, int& t1)
+{
+    wave_tiles_n<kWavesPerBlock>(ncells, wv, t0, t1);
 }
 
 // Stencil slot -> offset code d = (dx+1) + 3 (dy+1) + 9 (dz+1): the home

@@ -1,0 +1,205 @@
+// 2D potential of mean force and torque histogram (the paper's PMFT
+// section): for every ball pair (i, j) the bond d = p_j - q_i (minimum
+// image) is turned into the frame of the query point by its orientation,
+//     x' =  cos(theta_i) d_x + sin(theta_i) d_y
+//     y' = -sin(theta_i) d_x + cos(theta_i) d_y,
+// and counted in a uniform 2D histogram on [-x_max, x_max) x [-y_max, y_max).
+//
+// The pairs come from the ball query's cell list, one wavefront per home
+// cell, candidates in register slots, each query in scalar registers.  The
+// histogram is privatised per workgroup in LDS, keeping only the bins a bond
+// shorter than r_max can reach (the paper notes that multi-dimensional
+// histograms outgrow the caches first): at 200 x 200 bins on [-3, 3)^2 with
+// r_max = 3 that is about 129 KB, so one 1024-thread workgroup per CU holds
+// it.  Each workgroup writes its histogram to its own partial array and a
+// second kernel sums the partials into the caller's counts, so no global
+// atomics are needed.  Histograms too large for LDS use global atomics.
+#include "pair_common.hpp"
+
+namespace ppa {
+
+namespace {
+
+using namespace pair;
+
+constexpr int kPmftBlock = 1024;
+constexpr int kPmftWaves = kPmftBlock / kWave;
+constexpr int kPmftChunk = 4;  // slots per chunk of a stencil beyond 4 slots
+
+struct PmftLds {
+    float4 off[9];
+    StencilLds st[kPmftWaves];
+    int lo[kPmftMaxRows];
+    int base[kPmftMaxRows + 1];
+};
+
+// Bins one bond (lanes with `hit`).
+template <bool LDS>
+__device__ __forceinline__ void bin_bond(const PmftArgs& a, const PmftLds& L, unsigned* hist,
+                                         float dx, float dy, float cs, float sn)
+{
+    const float xr = fmaf(cs, dx, sn * dy);
+    const float yr = fmaf(cs, dy, -(sn * dx));
+    const float tx = (xr + a.x_max) * a.inv_dx;
+    const float ty = (yr + a.y_max) * a.inv_dy;
+    if (!(tx >= 0.f && tx < (float)a.nbx && ty >= 0.f && ty < (float)a.nby)) return;
+    const int ix = min((int)tx, a.nbx - 1);
+    const int iy = min((int)ty, a.nby - 1);
+    if (LDS) {
+        const int w = iy - L.lo[ix];
+        const int b = L.base[ix];
+        if (w >= 0 && w < L.base[ix + 1] - b) {
+            atomicAdd(&hist[b + w], 1u);
+            return;
+        }
+    }
+    atomicAdd(&a.counts[ix * a.nby + iy], 1u);
+}
+
+// The queries of one home cell against candidates [k0, k0 + 64 NS) of its
+// stencil.
+template <int NS, bool LDS>
+__device__ __forceinline__ void pmft_tile(const PmftArgs& a, const PairIn& in, const PmftLds& L,
+                                          const StencilLds& S, unsigned* hist, int C, int k0,
+                                          int q0, int q1, int lane)
+{
+    const PairGeom& G = a.geom;
+    Slots<2, NS> c;
+    c.load(in, G, S, L.off, k0, C, lane);
+    const float r2max = G.r2max;
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        QueryChunk Q;
+        Q.load(in, c0, q1 - c0, lane);
+        float sn = 0.f, cs = 1.f;
+        if (lane < Q.n) sincosf(a.angles[Q.my_id()], &sn, &cs);
+        for (int t = 0; t < Q.n; ++t) {
+            const float qx = lane_off(Q.q.x, t), qy = lane_off(Q.q.y, t);
+            const int qid = lane_of(Q.my_id(), t);
+            const float ct = lane_off(cs, t), st = lane_off(sn, t);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float dx = c.x[s] - qx, dy = c.y[s] - qy;
+                bool h = fmaf(dy, dy, dx * dx) < r2max;
+                if (a.excl) h = h && c.id[s] != qid;
+                if (h) bin_bond<LDS>(a, L, hist, dx, dy, ct, st);
+            }
+        }
+    }
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
+{
+    extern __shared__ unsigned s_hist[];
+    __shared__ PmftLds L;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = uniform(threadIdx.x / kWave);
+    const PairGeom& G = a.geom;
+    if (threadIdx.x < 9)
+        L.off[threadIdx.x] = make_float4(G.off[threadIdx.x][0], G.off[threadIdx.x][1], 0.f, 0.f);
+    if (LDS) {
+        for (int i = threadIdx.x; i < a.nbx; i += kPmftBlock) L.lo[i] = a.table.lo[i];
+        for (int i = threadIdx.x; i <= a.nbx; i += kPmftBlock) L.base[i] = a.table.base[i];
+        for (int i = threadIdx.x; i < a.words; i += kPmftBlock) s_hist[i] = 0u;
+    }
+    __syncthreads();
+    const PairIn in{a.cand, a.cand_start, a.qsorted, a.q_start};
+    StencilLds& S = L.st[wv];
+    int t0, t1;
+    wave_tiles_n<kPmftWaves>(G.ncells, wv, t0, t1);
+    for (int tile = t0; tile < t1; ++tile) {
+        const int q0 = in.q_start[tile];
+        const int q1 = in.q_start[tile + 1];
+        if (q0 == q1) continue;
+        const int C = stencil<2>(in, G, tile, lane, S);
+        const int ns = (C + kWave - 1) / kWave;
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: pmft_tile<N, LDS>(a, in, L, S, s_hist, C, 0, q0, q1, lane); break;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4)
+#undef PPA_CASE
+        default:
+            for (int k0 = 0; k0 < C; k0 += kPmftChunk * kWave)
+                pmft_tile<kPmftChunk, LDS>(a, in, L, S, s_hist, C, k0, q0, q1, lane);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        unsigned* out = a.partial + (size_t)blockIdx.x * a.words;
+        for (int i = threadIdx.x; i < a.words; i += kPmftBlock) out[i] = s_hist[i];
+    }
+}
+
+// counts[ix][iy] += sum over workgroups of their partial histograms.
+__global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __restrict__ partial,
+                                                          int blocks, int words, int nbx, int nby,
+                                                          PmftTable table,
+                                                          unsigned* __restrict__ counts)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbx * nby) return;
+    const int ix = b / nby, iy = b - ix * nby;
+    const int w = iy - table.lo[ix];
+    if (w < 0 || w >= table.base[ix + 1] - table.base[ix]) return;
+    const int idx = table.base[ix] + w;
+    unsigned sum = 0;
+    for (int g = 0; g < blocks; ++g) sum += partial[(size_t)g * words + idx];
+    counts[b] += sum;
+}
+
+}  // namespace
+
+// Workgroups of the LDS-histogram launch (one per CU when the histogram
+// fills most of the LDS), or of the global-atomics launch; a multiple of 8.
+int pmft_workgroups(int words)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                  ? prop.multiProcessorCount
+                  : 256;
+    }
+    const size_t lds = sizeof(unsigned) * (size_t)words;
+    int per_cu = 0;
+    hipError_t e = words > 0
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<true>,
+                                                                      kPmftBlock, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<false>,
+                                                                      kPmftBlock, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return (cus * per_cu + 7) / 8 * 8;
+}
+
+size_t pmft_lds_limit()
+{
+    static size_t limit = 0;
+    if (limit == 0) {
+        int dev = 0, v = 0;
+        limit = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            limit = (size_t)v;
+        limit -= sizeof(PmftLds) + 256;  // the static part of the kernel's LDS
+    }
+    return limit;
+}
+
+void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s)
+{
+    if (a.words > 0) {
+        const size_t lds = sizeof(unsigned) * (size_t)a.words;
+        (void)hipFuncSetAttribute((const void*)pmft_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(pmft_kernel<true>, dim3(blocks), dim3(kPmftBlock), lds, s, a);
+        const int nb = a.nbx * a.nby;
+        hipLaunchKernelGGL(pmft_reduce_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.partial,
+                           blocks, a.words, a.nbx, a.nby, a.table, a.counts);
+    } else {
+        hipLaunchKernelGGL(pmft_kernel<false>, dim3(blocks), dim3(kPmftBlock), 0, s, a);
+    }
+}
+
+}  // namespace ppa

@@ -181,3 +181,41 @@ def test_knn_workspace_and_argument_errors():
     assert call(guard=7.0) == ppa.PPA_ERANGE
     assert call(ws=0) == ppa.PPA_EWORKSPACE
     assert call(ws_bytes=64) == ppa.PPA_EWORKSPACE
+
+
+def test_normalisations_match_the_oracle_closed_forms():
+    """The binding's host-side normalisations against the oracle's."""
+    import oracle
+    rng = np.random.default_rng(2)
+    c = rng.integers(0, 1000, 64)
+    g = ppa.normalize_rdf(c, 5000, 4000, 1234.5, 0.5, 3.0, dim=3, n_frames=3)
+    np.testing.assert_allclose(g, oracle.rdf_normalize(c, 5000, 4000, 1234.5, 0.5, 3.0, 3, 3),
+                               rtol=1e-13)
+    g2 = ppa.normalize_rdf(c, 5000, 5000, 99.0, 0.0, 2.0, dim=2)
+    np.testing.assert_allclose(g2, oracle.rdf_normalize(c, 5000, 5000, 99.0, 0.0, 2.0, 2),
+                               rtol=1e-13)
+    cc = rng.integers(0, 50, (20, 30))
+    cc[3, 4] = 0
+    pcf, pmft = ppa.normalize_pmft2d(cc, 1000, 800, 345.0, 2.0, 3.0, n_frames=2)
+    ref = oracle.pmft2d_from_counts(cc, 1000, 800, 345.0, 2.0, 3.0, 2)
+    assert np.isinf(pmft[3, 4]) and np.isinf(ref[3, 4])
+    fin = np.isfinite(ref)
+    np.testing.assert_allclose(pmft[fin], ref[fin], rtol=1e-12, atol=1e-12)
+
+
+def test_pmft_workspace_and_errors():
+    b2 = ppa.Box((20.0, 20.0, 1.0), (0.1, 0.0, 0.0), 2)
+    small = ppa.pmft2d_workspace_bytes(b2, 1000, 0, 50, 50, 3.0, 3.0, 3.0)
+    assert small > 0
+    assert ppa.pmft2d_workspace_bytes(b2, 1000, 500, 50, 50, 3.0, 3.0, 3.0) > small
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.pmft2d_workspace_bytes(ppa.Box.cube(20.0), 1000, 0, 50, 50, 3.0, 3.0, 3.0)
+    assert e.value.code == ppa.PPA_EINVAL
+    for args in [(0, 50, 3.0, 3.0, 3.0), (50, 50, 0.0, 3.0, 3.0), (50, 50, 3.0, -1.0, 3.0),
+                 (50, 50, 3.0, 3.0, float("inf"))]:
+        with pytest.raises(ppa.PPAError) as e:
+            ppa.pmft2d_workspace_bytes(b2, 1000, 0, *args)
+        assert e.value.code == ppa.PPA_EINVAL
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.pmft2d_workspace_bytes(b2, 1000, 0, 50, 50, 3.0, 3.0, 10.0)
+    assert e.value.code == ppa.PPA_ERANGE
