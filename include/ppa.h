@@ -190,12 +190,45 @@ int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpt
                float y_max, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
                size_t ws_bytes, uint32_t* counts, hipStream_t stream);
 
+/* Gaussian-smoothed RDF (an extension beyond the paper: a differentiable
+ * form of the density module's RDF histogram).  With bins of width
+ * dr = r_max / bins centred at c_b = (b + 1/2) dr and
+ * phi(u) = exp(-u^2 / (2 sigma^2)) / (sigma sqrt(2 pi)):
+ *     h_b += dr * sum over ordered pairs (i, j), i != j, r_ij < r_max + 8 sigma
+ *            (minimum image), of phi(c_b - r_ij), for |c_b - r_ij| <= 8 sigma.
+ * The points query themselves; g_b = h_b / (N rho dV_b) as for the RDF.
+ *   bins in [1, 4096]; r_max + 8 sigma below half the smallest width.
+ *   h [bins] float64 device, accumulated.
+ *   flags: reserved, must be 0.
+ * Pair vectors enter the Gaussian in float64; its terms are float32 and are
+ * summed in float64. */
+int ppa_smooth_rdf_fwd(const ppa_box* box, const float* pts, int64_t n, int32_t bins, float r_max,
+                       float sigma, int32_t flags, void* ws, size_t ws_bytes, double* h,
+                       hipStream_t stream);
+
+/* Adjoint of ppa_smooth_rdf_fwd: given grad_h[b] = dL/dh_b (float64
+ * device), writes grad_pts[k] = dL/dp_k (float32 [n x 3] device):
+ *     dL/dp_k = sum over j != k of 2 A(r_kj) (p_k - p_j) / r_kj,
+ *     A(r) = sum_b grad_h[b] dr (c_b - r) / sigma^2 phi(c_b - r)
+ * over the same window; pairs at r = 0 add nothing.  The pairs are found
+ * again (nothing is kept from the forward); each row is summed in float64
+ * by the one wavefront that owns it. */
+int ppa_smooth_rdf_bwd(const ppa_box* box, const float* pts, int64_t n, int32_t bins, float r_max,
+                       float sigma, const double* grad_h, int32_t flags, void* ws,
+                       size_t ws_bytes, float* grad_pts, hipStream_t stream);
+
+/* Workspace bytes for ppa_smooth_rdf_fwd and ppa_smooth_rdf_bwd (the larger
+ * of the two).  Queries the current device, no device work. */
+int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, float r_max,
+                                   float sigma, size_t* bytes);
+
 /* Profiling hook: the next ppa_query_ball / ppa_rdf call made by this
  * thread records, on its stream, count_start / count_stop around its
  * row-count kernel and fill_start / fill_stop around its fill kernel (the
  * kernel that writes the list and the histogram; for ppa_query_knn, the two
  * selection kernels; for ppa_pmft2d, the binning and the sum of the
- * per-workgroup histograms), then forgets them.  Any
+ * per-workgroup histograms; for the smoothed RDF, its pair kernel and, in
+ * the forward, the sum of the partial histograms), then forgets them.  Any
  * event may be NULL; the events belong to the caller.  Used to time single
  * kernels inside a longer stream of work. */
 int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,

@@ -111,6 +111,9 @@ def lib():
             "ppa_pmft2d_workspace_bytes": [BP, i64, i64, i32, i32, f32, f32, f32,
                                            ctypes.POINTER(sz)],
             "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
+            "ppa_smooth_rdf_workspace_bytes": [BP, i64, i32, f32, f32, ctypes.POINTER(sz)],
+            "ppa_smooth_rdf_fwd": [BP, P, i64, i32, f32, f32, i32, P, sz, P, P],
+            "ppa_smooth_rdf_bwd": [BP, P, i64, i32, f32, f32, P, i32, P, sz, P, P],
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
         }
@@ -401,6 +404,99 @@ def normalize_pmft2d(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
     with np.errstate(divide="ignore"):
         pmft = -np.log(pcf)
     return pcf, pmft
+
+
+def smooth_rdf_workspace_bytes(box: Box, n, bins, r_max, sigma):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_smooth_rdf_workspace_bytes(ctypes.byref(box.c()), int(n), int(bins),
+                                                float(r_max), float(sigma), ctypes.byref(out)))
+    return out.value
+
+
+def smooth_rdf_h(box: Box, points, bins, r_max, sigma, h=None, ws=None, stream=None, check=True):
+    """Gaussian-smoothed RDF numerator h (float64 [bins], accumulated into `h`)."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    if h is None:
+        h = torch.zeros(int(bins), dtype=torch.float64, device=pts.device)
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(smooth_rdf_workspace_bytes(box, n, bins, r_max, sigma))
+    _check(lib().ppa_smooth_rdf_fwd(ctypes.byref(box.c()), _ptr(pts), n, int(bins), float(r_max),
+                                    float(sigma), 0, wptr, wlen, _ptr(h), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return h
+
+
+def smooth_rdf_grad(box: Box, points, bins, r_max, sigma, grad_h, ws=None, stream=None,
+                    check=True):
+    """dL/dpoints (float32 [n, 3]) given dL/dh (float64 [bins]); pairs are found again."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    gh = grad_h
+    if not isinstance(gh, torch.Tensor):
+        gh = torch.as_tensor(np.ascontiguousarray(gh, dtype=np.float64))
+    gh = gh.to(device=pts.device, dtype=torch.float64).contiguous()
+    if gh.shape != (int(bins),):
+        raise ValueError("grad_h must have one entry per bin")
+    out = torch.empty((n, 3), dtype=torch.float32, device=pts.device)
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(smooth_rdf_workspace_bytes(box, n, bins, r_max, sigma))
+    _check(lib().ppa_smooth_rdf_bwd(ctypes.byref(box.c()), _ptr(pts), n, int(bins), float(r_max),
+                                    float(sigma), _ptr(gh), 0, wptr, wlen, _ptr(out),
+                                    _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return out
+
+
+def _smooth_function():
+    torch = _torch()
+
+    class SmoothRDF(torch.autograd.Function):
+        """h = smoothed RDF numerator of `points` (float64 [bins]); its backward
+        runs the library's adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, points, box, bins, r_max, sigma):
+            ctx.save_for_backward(points)
+            ctx.cfg = (box, int(bins), float(r_max), float(sigma))
+            return smooth_rdf_h(box, points.detach(), bins, r_max, sigma)
+
+        @staticmethod
+        def backward(ctx, grad_h):
+            (points,) = ctx.saved_tensors
+            box, bins, r_max, sigma = ctx.cfg
+            g = smooth_rdf_grad(box, points.detach(), bins, r_max, sigma, grad_h)
+            return g.to(points.dtype), None, None, None, None
+
+    return SmoothRDF
+
+
+_SmoothRDF = None
+
+
+def smooth_rdf(points, box: Box, bins, r_max, sigma):
+    """Differentiable smoothed RDF numerator h (float64 [bins]) of a float32
+    [n, 3] CUDA tensor of positions."""
+    global _SmoothRDF
+    if _SmoothRDF is None:
+        _SmoothRDF = _smooth_function()
+    return _SmoothRDF.apply(points, box, bins, r_max, sigma)
+
+
+def smooth_rdf_g(h, n_points, volume, r_max, dim=3):
+    """g_b = h_b / (N rho dV_b) on the bins of [0, r_max) (differentiable in h)."""
+    torch = _torch()
+    bins = h.shape[-1]
+    e = np.arange(bins + 1, dtype=np.float64) * (float(r_max) / bins)
+    dv = (4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)) if dim == 3 else \
+        math.pi * (e[1:] ** 2 - e[:-1] ** 2)
+    scale = torch.as_tensor(1.0 / (n_points * (n_points / volume) * dv), dtype=h.dtype,
+                            device=h.device)
+    return h * scale
 
 
 def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream=None):

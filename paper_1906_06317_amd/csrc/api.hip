@@ -593,6 +593,110 @@ int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// ---------------------------------------------------------------------------
+// Gaussian-smoothed RDF: plan, workspace and launches.
+// ---------------------------------------------------------------------------
+struct SmoothPlan {
+    Grid g;
+    double r_s;  // pair cutoff r_max + 8 sigma
+    int blocks;
+};
+
+int smooth_plan(const BoxPrep& bp, int64_t n, int32_t bins, float r_max, float sigma, bool adjoint,
+                SmoothPlan* P)
+{
+    if (bins < 1 || bins > kSmoothMaxBins)
+        return set_error(PPA_EINVAL, "bins must be in [1, %d]", kSmoothMaxBins);
+    if (!(isfinite(r_max) && r_max > 0.f)) return set_error(PPA_EINVAL, "r_max must be positive");
+    if (!(isfinite(sigma) && sigma > 0.f)) return set_error(PPA_EINVAL, "sigma must be positive");
+    P->r_s = (double)r_max + 8.0 * (double)sigma;
+    int rc;
+    if ((rc = check_cutoff(bp, P->r_s))) return rc;
+    make_grid(bp, P->r_s, n, &P->g);
+    P->blocks = smooth_workgroups(adjoint, bp.dim);
+    return PPA_OK;
+}
+
+size_t smooth_layout(const SmoothPlan& P, int64_t n, int32_t bins, void* base_v, Workspace* W,
+                     double** partial)
+{
+    char* base = (char*)base_v;
+    size_t off = workspace_layout(P.g, n, 0, 0, base_v, W);
+    *partial = base ? (double*)(base + off) : nullptr;
+    off += sizeof(double) * (size_t)P.blocks * (size_t)bins;
+    return (off + 255) & ~(size_t)255;
+}
+
+int run_smooth(const ppa_box* box, const float* pts, int64_t n, int32_t bins, float r_max,
+               float sigma, const double* grad_h, int32_t flags, void* ws, size_t ws_bytes,
+               double* h, float* grad, hipStream_t s)
+{
+    const bool adjoint = grad != nullptr;
+    if (!pts && n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (n < 0 || n > 0x7fffffffLL) return set_error(PPA_EINVAL, "bad point count");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    if (adjoint ? !grad_h : !h) return set_error(PPA_EINVAL, "output or gradient pointer is NULL");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    SmoothPlan P;
+    if ((rc = smooth_plan(bp, n, bins, r_max, sigma, adjoint, &P))) return rc;
+    Workspace W{};
+    double* partial = nullptr;
+    const size_t need = smooth_layout(P, n, bins, nullptr, &W, &partial);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    smooth_layout(P, n, bins, ws, &W, &partial);
+    if (n == 0) return PPA_OK;
+    const Grid& g = P.g;
+    launch_zero(W, g, false, nullptr, 0, s);
+    launch_build_cells(pts, W.pts, bp, g, W.status, s);
+
+    SmoothArgs A{};
+    A.cand = W.pts.local;
+    A.cand_start = W.pts.cell_start;
+    for (int d = 0; d < 3; ++d) A.geom.n[d] = g.n[d];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    A.geom.r2max = (float)(P.r_s * P.r_s);
+    // the stencil offsets again in float64, for the exact pair vectors
+    for (int t = 0; t < 27; ++t) {
+        const int centre = g.nsten / 2;
+        const int code = t == 0 ? centre : (t == centre ? 0 : t);
+        double d[3] = {(double)(code % 3 - 1), (double)((code / 3) % 3 - 1),
+                       bp.dim == 3 ? (double)(code / 9 - 1) : 0.0};
+        if (t >= g.nsten) d[0] = d[1] = d[2] = 0.0;
+        const double f[3] = {d[0] / g.n[0], d[1] / g.n[1], d[2] / g.n[2]};
+        A.offd[t][0] = bp.M[0][0] * f[0] + bp.M[0][1] * f[1] + bp.M[0][2] * f[2];
+        A.offd[t][1] = bp.M[1][1] * f[1] + bp.M[1][2] * f[2];
+        A.offd[t][2] = bp.dim == 3 ? bp.M[2][2] * f[2] : 0.0;
+    }
+    A.bins = bins;
+    A.dr = (double)r_max / bins;
+    A.w8 = 8.0 * (double)sigma;
+    const double sg = sigma;
+    A.k2 = (float)(1.4426950408889634 / (2.0 * sg * sg));
+    A.hscale = (float)(A.dr / (sg * sqrt(2.0 * M_PI)));
+    A.gscale = (float)(A.dr / (sg * sg * sg * sqrt(2.0 * M_PI)));
+    A.partial = partial;
+    A.h = h;
+    A.grad_h = grad_h;
+    A.grad = grad;
+    long long want = ((long long)g.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    int blocks = (int)(want < P.blocks ? (want + 7) / 8 * 8 : P.blocks);
+    if (blocks > P.blocks) blocks = P.blocks;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], s);
+    if (adjoint)
+        launch_smooth_bwd(A, bp.dim, blocks, s);
+    else
+        launch_smooth_fwd(A, bp.dim, blocks, s);
+    record(pe.ev[3], s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -729,6 +833,42 @@ int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpt
 {
     return run_pmft(box, pts, n, qpts, angles, nq, nbx, nby, x_max, y_max, r_max, exclude_ii,
                     flags, ws, ws_bytes, counts, stream);
+}
+
+int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, float r_max,
+                                   float sigma, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0) return set_error(PPA_EINVAL, "negative point count");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    SmoothPlan P, Pb;
+    if ((rc = smooth_plan(bp, n, bins, r_max, sigma, false, &P))) return rc;
+    if ((rc = smooth_plan(bp, n, bins, r_max, sigma, true, &Pb))) return rc;
+    Workspace W{};
+    double* partial = nullptr;
+    const size_t a = smooth_layout(P, n, bins, nullptr, &W, &partial);
+    const size_t b = smooth_layout(Pb, n, bins, nullptr, &W, &partial);
+    *bytes = a > b ? a : b;
+    return PPA_OK;
+}
+
+int ppa_smooth_rdf_fwd(const ppa_box* box, const float* pts, int64_t n, int32_t bins, float r_max,
+                       float sigma, int32_t flags, void* ws, size_t ws_bytes, double* h,
+                       hipStream_t stream)
+{
+    return run_smooth(box, pts, n, bins, r_max, sigma, nullptr, flags, ws, ws_bytes, h, nullptr,
+                      stream);
+}
+
+int ppa_smooth_rdf_bwd(const ppa_box* box, const float* pts, int64_t n, int32_t bins, float r_max,
+                       float sigma, const double* grad_h, int32_t flags, void* ws,
+                       size_t ws_bytes, float* grad_pts, hipStream_t stream)
+{
+    if (!grad_pts) return set_error(PPA_EINVAL, "grad_pts is NULL");
+    return run_smooth(box, pts, n, bins, r_max, sigma, grad_h, flags, ws, ws_bytes, nullptr,
+                      grad_pts, stream);
 }
 
 int ppa_sync_status(const void* ws, hipStream_t stream)

@@ -196,6 +196,30 @@ int pmft_workgroups(int words);
 size_t pmft_lds_limit();  // bytes of LDS a workgroup may give the histogram
 void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s);
 
+// Gaussian-smoothed RDF and its adjoint (smooth.hip).
+constexpr int kSmoothMaxBins = 4096;
+
+struct SmoothArgs {
+    const float4* cand;       // points sorted by cell (they are also the queries)
+    const int* cand_start;    // [ncells + 1]
+    PairGeom geom;            // r2max = (r_max + 8 sigma)^2 in float
+    double offd[27][3];       // stencil offsets in float64
+    int bins;
+    double dr;                // r_max / bins
+    double w8;                // window half-width 8 sigma
+    float k2;                 // log2(e) / (2 sigma^2)
+    float hscale;             // dr / (sigma sqrt(2 pi)): forward weight of exp(-u^2/2s^2)
+    float gscale;             // dr / (sigma^3 sqrt(2 pi)): adjoint weight of u exp(-u^2/2s^2)
+    double* partial;          // forward: [gridDim.x][bins]
+    double* h;                // forward: [bins], accumulated
+    const double* grad_h;     // adjoint: dL/dh [bins]
+    float* grad;              // adjoint: dL/dp [n][3], written
+};
+
+int smooth_workgroups(bool adjoint, int dim);
+void launch_smooth_fwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s);
+void launch_smooth_bwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s);
+
 void launch_hist_from_dist(const float* dist, const int64_t* n_pairs, int64_t capacity, int bins,
                            float r_min, float inv_dr, unsigned long long* hist, hipStream_t s);
 
