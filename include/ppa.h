@@ -222,6 +222,82 @@ int ppa_smooth_rdf_bwd(const ppa_box* box, const float* pts, int64_t n, int32_t 
 int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, float r_max,
                                    float sigma, size_t* bytes);
 
+/* ---- Batched analysis (an extension beyond the paper) --------------------
+ * Many frames (a trajectory, or many systems of uneven size each with its
+ * own box) analysed together: for every frame the ball-query NeighborList
+ * and the RDF, as ppa_rdf computes them for that frame alone, in one fixed
+ * sequence of launches over one cell list holding every frame's cells.  The
+ * paper accumulates an RDF over frames by calling compute once per frame
+ * (reset=False); a batch does all frames at once and keeps one histogram
+ * per frame. */
+typedef struct ppa_batch_plan_s ppa_batch_plan;
+typedef struct ppa_batch_graph_s ppa_batch_graph;
+
+/* Plan for n_frames frames: boxes[f] (host), and the points of frame f are
+ * rows frame_offsets[f] .. frame_offsets[f+1] - 1 of one [N x 3] float32
+ * array (frame_offsets: host, n_frames + 1 entries, starting at 0,
+ * non-decreasing, N = frame_offsets[n_frames] < 2^31).  All frames share
+ * the dimension, bins, r_min, r_max and exclude_ii (each frame's points
+ * query themselves).  r_max must be below half the smallest perpendicular
+ * width of every frame (PPA_ERANGE names the frame).  flags: reserved, 0.
+ * Host only; free with ppa_batch_plan_destroy. */
+int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t* frame_offsets,
+                          int32_t bins, float r_min, float r_max, int32_t exclude_ii,
+                          int32_t flags, ppa_batch_plan** out);
+int ppa_batch_plan_destroy(ppa_batch_plan* plan);
+
+/* Workspace bytes a plan needs (every launch configuration fits in it). */
+int ppa_batch_workspace_bytes(const ppa_batch_plan* plan, size_t* bytes);
+
+/* Copies the plan's frame tables into the workspace (asynchronous on the
+ * stream; the plan owns the host copies).  Needed once per workspace,
+ * before ppa_batch_run, ppa_batch_autotune or ppa_batch_graph_create. */
+int ppa_batch_upload(ppa_batch_plan* plan, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One batched run in the plan's current configuration.
+ *   pts [N x 3] float32 device.
+ *   hist [n_frames x bins] uint64 device, accumulated: row f is frame f's RDF
+ *     pair histogram (as ppa_rdf with that frame's points and box).
+ *   offsets [N + 1] int64 device: one CSR over all frames' rows in point
+ *     order; counts [N] int32 device or NULL.
+ *   point_idx [capacity] int32: neighbour indices local to the frame (0 is
+ *     the frame's first point); dist [capacity] float32 or NULL.
+ *   n_pairs_dev: int64 device, total pairs (PPA_ECAPACITY when above
+ *     capacity, reported by ppa_sync_status).
+ * Only kernels are launched (no copies, no memsets, no allocation), so a
+ * run can be captured in a HIP graph. */
+int ppa_batch_run(ppa_batch_plan* plan, const float* pts, void* ws, size_t ws_bytes,
+                  uint64_t* hist, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                  float* dist, int64_t capacity, int64_t* n_pairs_dev, hipStream_t stream);
+
+/* Launch configurations: index >= 0 selects one, -1 only queries.  Returns
+ * the number of configurations, the current one, and its cell width
+ * (cell_scale * r_max at least) and resident workgroups per CU of the pair
+ * kernels (0: as many as fit).  Any pointer may be NULL. */
+int ppa_batch_config(ppa_batch_plan* plan, int32_t index, int32_t* n_configs, int32_t* chosen,
+                     double* cell_scale, int32_t* blocks_per_cu);
+
+/* Autotuner: runs every configuration (one warm-up and `reps` timed runs,
+ * HIP events on the stream, which it synchronizes) and selects the fastest
+ * for later runs and graphs.  The NeighborList arguments are used as
+ * scratch (they hold the last trial's list); histograms go to scratch in the
+ * workspace.  ms_out [n_configs] host or NULL receives the mean times. */
+int ppa_batch_autotune(ppa_batch_plan* plan, const float* pts, void* ws, size_t ws_bytes,
+                       int64_t* offsets, int32_t* counts, int32_t* point_idx, float* dist,
+                       int64_t capacity, int64_t* n_pairs_dev, int32_t reps, hipStream_t stream,
+                       float* ms_out);
+
+/* Captures one ppa_batch_run with these arguments (the plan's current
+ * configuration) into an instantiated HIP graph; ppa_batch_graph_launch
+ * replays it on a stream with one launch.  The arguments must stay valid
+ * for the graph's life. */
+int ppa_batch_graph_create(ppa_batch_plan* plan, const float* pts, void* ws, size_t ws_bytes,
+                           uint64_t* hist, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                           float* dist, int64_t capacity, int64_t* n_pairs_dev,
+                           ppa_batch_graph** out);
+int ppa_batch_graph_launch(ppa_batch_graph* graph, hipStream_t stream);
+int ppa_batch_graph_destroy(ppa_batch_graph* graph);
+
 /* Profiling hook: the next ppa_query_ball / ppa_rdf call made by this
  * thread records, on its stream, count_start / count_stop around its
  * row-count kernel and fill_start / fill_stop around its fill kernel (the

@@ -112,6 +112,18 @@ def lib():
                                            ctypes.POINTER(sz)],
             "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
             "ppa_smooth_rdf_workspace_bytes": [BP, i64, i32, f32, f32, ctypes.POINTER(sz)],
+            "ppa_batch_plan_create": [i32, BP, P, i32, f32, f32, i32, i32,
+                                      ctypes.POINTER(ctypes.c_void_p)],
+            "ppa_batch_plan_destroy": [P],
+            "ppa_batch_workspace_bytes": [P, ctypes.POINTER(sz)],
+            "ppa_batch_upload": [P, P, sz, P],
+            "ppa_batch_run": [P, P, P, sz, P, P, P, P, P, i64, P, P],
+            "ppa_batch_config": [P, i32, P, P, P, P],
+            "ppa_batch_autotune": [P, P, P, sz, P, P, P, P, i64, P, i32, P, P],
+            "ppa_batch_graph_create": [P, P, P, sz, P, P, P, P, P, i64, P,
+                                       ctypes.POINTER(ctypes.c_void_p)],
+            "ppa_batch_graph_launch": [P, P],
+            "ppa_batch_graph_destroy": [P],
             "ppa_smooth_rdf_fwd": [BP, P, i64, i32, f32, f32, i32, P, sz, P, P],
             "ppa_smooth_rdf_bwd": [BP, P, i64, i32, f32, f32, P, i32, P, sz, P, P],
             "ppa_sync_status": [P, P],
@@ -497,6 +509,116 @@ def smooth_rdf_g(h, n_points, volume, r_max, dim=3):
     scale = torch.as_tensor(1.0 / (n_points * (n_points / volume) * dv), dtype=h.dtype,
                             device=h.device)
     return h * scale
+
+
+class BatchPlan:
+    """Batched ball query + per-frame RDF over many frames, each with its own
+    box (frames are consecutive row ranges of one [N, 3] point array).
+
+    run() returns (hist [n_frames, bins] int64, NeighborList over all rows
+    with frame-local point indices); graph() captures a run in a HIP graph."""
+
+    def __init__(self, boxes, frame_sizes, bins, r_max, r_min=0.0, exclude_ii=True,
+                 capacity=None):
+        torch = _torch()
+        self.boxes = list(boxes)
+        sizes = np.asarray(frame_sizes, dtype=np.int64)
+        self.offsets_host = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.n_frames = len(self.boxes)
+        if sizes.shape[0] != self.n_frames:
+            raise ValueError("one size per box is required")
+        self.n = int(self.offsets_host[-1])
+        self.bins = int(bins)
+        self.r_max, self.r_min = float(r_max), float(r_min)
+        cboxes = (CBox * self.n_frames)(*[b.c() for b in self.boxes])
+        h = ctypes.c_void_p()
+        _check(lib().ppa_batch_plan_create(self.n_frames, cboxes,
+                                           self.offsets_host.ctypes.data_as(ctypes.c_void_p),
+                                           self.bins, self.r_min, self.r_max,
+                                           int(bool(exclude_ii)), 0, ctypes.byref(h)))
+        self._h = h
+        need = ctypes.c_size_t(0)
+        _check(lib().ppa_batch_workspace_bytes(self._h, ctypes.byref(need)))
+        self.ws = Workspace()
+        self.wptr, self.wlen = self.ws.get(need.value)
+        _check(lib().ppa_batch_upload(self._h, self.wptr, self.wlen, _stream()))
+        if capacity is None:
+            capacity = sum(_estimate_pairs(b, int(m), int(m), r_max) for b, m in zip(self.boxes, sizes))
+        self.capacity = int(capacity)
+        dev = "cuda"
+        self.offsets = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        self.counts = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self.point_idx = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.dist = torch.empty(max(self.capacity, 1), dtype=torch.float32, device=dev)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._graph = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_graph", None):
+                lib().ppa_batch_graph_destroy(self._graph)
+            if getattr(self, "_h", None):
+                lib().ppa_batch_plan_destroy(self._h)
+        except Exception:
+            pass
+
+    def _out(self):
+        return (_ptr(self.offsets), _ptr(self.counts), _ptr(self.point_idx), _ptr(self.dist),
+                self.capacity, _ptr(self.n_pairs))
+
+    def config(self, index=-1):
+        n, c, scale, cap = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(),
+                            ctypes.c_int32())
+        _check(lib().ppa_batch_config(self._h, int(index), ctypes.byref(n), ctypes.byref(c),
+                                      ctypes.byref(scale), ctypes.byref(cap)))
+        return {"n_configs": n.value, "chosen": c.value, "cell_scale": scale.value,
+                "blocks_per_cu": cap.value}
+
+    def autotune(self, points, reps=3, stream=None):
+        """Times every launch configuration on these points and keeps the fastest."""
+        pts = _points(points)
+        n = self.config()["n_configs"]
+        ms = (ctypes.c_float * n)()
+        o = self._out()
+        _check(lib().ppa_batch_autotune(self._h, _ptr(pts), self.wptr, self.wlen, o[0], o[1], o[2],
+                                        o[3], o[4], o[5], int(reps), _stream(stream), ms))
+        return list(ms), self.config()
+
+    def run(self, points, hist=None, stream=None, check=True):
+        torch = _torch()
+        pts = _points(points)
+        if pts.shape[0] != self.n:
+            raise ValueError("points must hold every frame's rows")
+        if hist is None:
+            hist = torch.zeros((self.n_frames, self.bins), dtype=torch.int64, device=pts.device)
+        o = self._out()
+        _check(lib().ppa_batch_run(self._h, _ptr(pts), self.wptr, self.wlen, _ptr(hist), *o,
+                                   _stream(stream)))
+        if check:
+            _check(self.ws.status(stream))
+        return hist, self.neighbor_list()
+
+    def neighbor_list(self):
+        np_ = int(self.n_pairs.item())
+        return NeighborList(self.offsets, self.counts, self.point_idx[:np_], self.dist[:np_], np_)
+
+    def graph(self, points, hist):
+        """Captures a run with these (device-resident) points and histogram; the
+        returned callable replays it on a stream with one graph launch."""
+        pts = _points(points)
+        if self._graph:
+            lib().ppa_batch_graph_destroy(self._graph)
+            self._graph = None
+        g = ctypes.c_void_p()
+        o = self._out()
+        _check(lib().ppa_batch_graph_create(self._h, _ptr(pts), self.wptr, self.wlen, _ptr(hist),
+                                            *o, ctypes.byref(g)))
+        self._graph = g
+        self._graph_args = (pts, hist)  # keep them alive with the graph
+
+        def launch(stream=None):
+            _check(lib().ppa_batch_graph_launch(self._graph, _stream(stream)))
+        return launch
 
 
 def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream=None):

@@ -169,37 +169,6 @@ size_t workspace_layout(const Grid& g, int64_t n, int64_t nq, int32_t flags, voi
     return off;
 }
 
-}  // namespace ppa
-
-using namespace ppa;
-
-namespace {
-
-struct QueryCall {
-    const ppa_box* box;
-    const float* pts;
-    int64_t n;
-    const float* qpts;
-    int64_t nq;
-    float r_max;
-    int32_t exclude_ii;
-    int32_t flags;
-    void* ws;
-    size_t ws_bytes;
-    bool want_nl;
-    int64_t* offsets;
-    int32_t* counts;
-    int32_t* point_idx;
-    float* dist;
-    int64_t capacity;
-    int64_t* n_pairs_dev;
-    bool want_hist;
-    int32_t bins;
-    float r_min;
-    uint64_t* hist;
-    hipStream_t stream;
-};
-
 int check_cutoff(const BoxPrep& bp, double r)
 {
     const double half = 0.5 * fmin(bp.width[0], fmin(bp.width[1], bp.width[2]));
@@ -235,6 +204,37 @@ bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r)
                             3 * qmax * qmax + (r * r + qmax * qmax));
     return err <= 0.5e-5 * r * r;
 }
+
+}  // namespace ppa
+
+using namespace ppa;
+
+namespace {
+
+struct QueryCall {
+    const ppa_box* box;
+    const float* pts;
+    int64_t n;
+    const float* qpts;
+    int64_t nq;
+    float r_max;
+    int32_t exclude_ii;
+    int32_t flags;
+    void* ws;
+    size_t ws_bytes;
+    bool want_nl;
+    int64_t* offsets;
+    int32_t* counts;
+    int32_t* point_idx;
+    float* dist;
+    int64_t capacity;
+    int64_t* n_pairs_dev;
+    bool want_hist;
+    int32_t bins;
+    float r_min;
+    uint64_t* hist;
+    hipStream_t stream;
+};
 
 int run_pairs(const QueryCall& c)
 {

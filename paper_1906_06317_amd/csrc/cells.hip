@@ -32,16 +32,15 @@ __global__ void zero_kernel(ZeroRanges z)
     }
 }
 
-// Cell index and cell-centred local coordinates, in float64.
-__global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ pts, int64_t n,
-                                                     AssignBox B, int* __restrict__ cell_of,
-                                                     int* __restrict__ slot,
-                                                     float4* __restrict__ local,
-                                                     int* __restrict__ cell_count,
-                                                     unsigned* __restrict__ status)
+// Cell index and cell-centred local coordinates of point i, in float64;
+// cells of this box are numbered from cell_base.
+__device__ __forceinline__ void assign_point(const float* __restrict__ pts, int64_t i,
+                                             const AssignBox& B, int cell_base,
+                                             int* __restrict__ cell_of, int* __restrict__ slot,
+                                             float4* __restrict__ local,
+                                             int* __restrict__ cell_count,
+                                             unsigned* __restrict__ status)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     double p0 = (double)pts[3 * i];
     double p1 = (double)pts[3 * i + 1];
     double p2 = B.dim == 3 ? (double)pts[3 * i + 2] : 0.0;
@@ -68,10 +67,58 @@ __global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ p
     const double x = B.M[0][0] * f[0] + B.M[0][1] * f[1] + B.M[0][2] * f[2];
     const double y = B.M[1][1] * f[1] + B.M[1][2] * f[2];
     const double z = B.M[2][2] * f[2];
-    const int cell = (c[2] * B.ni[1] + c[1]) * B.ni[0] + c[0];
+    const int cell = cell_base + (c[2] * B.ni[1] + c[1]) * B.ni[0] + c[0];
     cell_of[i] = cell;
     local[i] = make_float4((float)x, (float)y, (float)z, __int_as_float((int)i));
     slot[i] = atomicAdd(&cell_count[cell], 1);
+}
+
+__global__ void __launch_bounds__(256) assign_kernel(const float* pts, int64_t n, AssignBox B,
+                                                     int* cell_of, int* slot, float4* local,
+                                                     int* cell_count, unsigned* status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    assign_point(pts, i, B, 0, cell_of, slot, local, cell_count, status);
+}
+
+// A batch: every point finds its frame (point_base[f] <= i < point_base[f+1])
+// and is assigned in that frame's box; the cells of frame f are numbered
+// from its cell_base, so all frames share one list.
+__global__ void __launch_bounds__(256) assign_batch_kernel(const float* pts, int64_t n,
+                                                           const FrameInfo* __restrict__ frames,
+                                                           const int* __restrict__ point_base,
+                                                           int nframes, int* cell_of, int* slot,
+                                                           float4* local, int* cell_count,
+                                                           unsigned* status)
+{
+    __shared__ int s_f;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nframes - 1;  // last frame starting at or before `first`
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (point_base[mid] <= first)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_f = lo;
+    }
+    __syncthreads();
+    const int64_t i = first + threadIdx.x;
+    if (i >= n) return;
+    int f = s_f;
+    while (f + 1 < nframes && point_base[f + 1] <= i) ++f;
+    // one pass per distinct frame of the wave, so each box is read uniformly
+    for (;;) {
+        const int fu = __builtin_amdgcn_readfirstlane(f);
+        if (f == fu) {
+            assign_point(pts, i, frames[fu].box, frames[fu].cell_base, cell_of, slot, local,
+                         cell_count, status);
+            break;
+        }
+    }
 }
 
 // Place every point in its cell's run at the slot its atomic returned (the
@@ -272,6 +319,24 @@ void launch_zero(Workspace& ws, const Grid& g, bool separate_queries, void* extr
     hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, s, z);
 }
 
+// Counting sort of the assigned points into their cells: scan of the cell
+// counts, scatter in arrival order, then ranks by index within each cell.
+static void finish_cells(CellList& cl, int ncells, hipStream_t s)
+{
+    const int64_t n = cl.n;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    launch_scan<int>(cl.cell_count, cl.cell_start, ncells, cl.scan_flags, cl.scan_ticket, nullptr,
+                     s);
+    if (n > 0) {
+        // arrival order into `sorted`, then ranked by index back into `local`,
+        // which from here on holds the final cell-sorted points
+        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.slot,
+                           cl.local, cl.cell_start, cl.sorted);
+        hipLaunchKernelGGL(rank_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of,
+                           cl.cell_start, cl.sorted, cl.local);
+    }
+}
+
 void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const Grid& g,
                         unsigned* status, hipStream_t s)
 {
@@ -292,16 +357,20 @@ void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const 
     if (n > 0)
         hipLaunchKernelGGL(assign_kernel, dim3(blocks), dim3(256), 0, s, pts, n, ab, cl.cell_of,
                            cl.slot, cl.local, cl.cell_count, status);
-    launch_scan<int>(cl.cell_count, cl.cell_start, g.ncells, cl.scan_flags, cl.scan_ticket,
-                     nullptr, s);
-    if (n > 0) {
-        // arrival order into `sorted`, then ranked by index back into `local`,
-        // which from here on holds the final cell-sorted points
-        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.slot,
-                           cl.local, cl.cell_start, cl.sorted);
-        hipLaunchKernelGGL(rank_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of,
-                           cl.cell_start, cl.sorted, cl.local);
-    }
+    finish_cells(cl, g.ncells, s);
+}
+
+void launch_build_cells_batch(const float* pts, CellList& cl, const FrameInfo* frames,
+                              const int* point_base, int nframes, int ncells, unsigned* status,
+                              hipStream_t s)
+{
+    const int64_t n = cl.n;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (n > 0)
+        hipLaunchKernelGGL(assign_batch_kernel, dim3(blocks), dim3(256), 0, s, pts, n, frames,
+                           point_base, nframes, cl.cell_of, cl.slot, cl.local, cl.cell_count,
+                           status);
+    finish_cells(cl, ncells, s);
 }
 
 }  // namespace ppa

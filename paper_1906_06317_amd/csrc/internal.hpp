@@ -73,6 +73,16 @@ struct Workspace {
     size_t bytes;
 };
 
+// One frame of a batch as the kernels see it (a table in the workspace).
+struct FrameInfo {
+    AssignBox box;         // float64 box and cell grid of the frame
+    int cell_base;         // first global cell id of the frame
+    int nsten;             // 27 in 3D, 9 in 2D
+    int dot;               // expanded in/out test allowed for this frame's cells
+    int point_base;        // first global point index of the frame
+    float off[27][4];      // stencil offsets M (delta / n), float32
+};
+
 // Host helpers (api.hip).
 int prepare_box(const ppa_box* box, BoxPrep* out);
 int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g);
@@ -91,6 +101,12 @@ void launch_scan_i64(const int* in, int64_t* out, int64_t n, unsigned long long*
 void launch_scan_i64_total(const int* in, int64_t* out, int64_t n, unsigned long long* flags,
                            int* ticket, unsigned long long* total, hipStream_t s);
 size_t scan_flag_count(int64_t n);
+// Batch: cells of every frame in one global list (cells.hip).
+void launch_build_cells_batch(const float* pts, CellList& cl, const FrameInfo* frames,
+                              const int* point_base, int nframes, int ncells, unsigned* status,
+                              hipStream_t s);
+bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r);
+int check_cutoff(const BoxPrep& bp, double r);
 
 // Geometry of a pair query (pairs.hip).
 struct PairGeom {
@@ -120,6 +136,19 @@ struct PairArgs {
     float r_min;
     float inv_dr;
 };
+
+// Batch pair kernels: frames[] and cell_base[nframes + 1] in device memory.
+struct BatchGeom {
+    const FrameInfo* frames;
+    const int* cell_base;
+    int nframes;
+    int ncells;        // all frames
+    float r2max;
+};
+void launch_count_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
+                        hipStream_t s);
+void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
+                       hipStream_t s);
 
 // excl: 0 keep i == j, 1 points query themselves (drop the query's own
 // entry), 2 separate query points (drop j == i by index).

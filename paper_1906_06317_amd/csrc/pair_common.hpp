@@ -94,29 +94,31 @@ __device__ __forceinline__ int stencil_code(int s, int nsten)
     return s == 0 ? centre : (s == centre ? 0 : s);
 }
 
-// Stencil of home cell `tile`: per-offset starts and prefix counts in LDS;
-// returns the candidate count C (uniform).
+// Stencil of home cell `tile` (a global cell id; its frame's cells start at
+// cell_base and form an n0 x n1 x n2 grid): per-offset starts and prefix
+// counts in LDS; returns the candidate count C (uniform).
 template <int DIM>
-__device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int tile, int lane,
-                                       StencilLds& S)
+__device__ __forceinline__ int stencil(const PairIn& in, int n0, int n1, int n2, int nsten,
+                                       int cell_base, int tile, int lane, StencilLds& S)
 {
-    const int cx = tile % G.n[0];
-    const int rest = tile / G.n[0];
-    const int cy = rest % G.n[1];
-    const int cz = rest / G.n[1];
+    const int local = tile - cell_base;
+    const int cx = local % n0;
+    const int rest = local / n0;
+    const int cy = rest % n1;
+    const int cz = rest / n1;
     int cnt = 0, st = 0;
-    if (lane < G.nsten) {
+    if (lane < nsten) {
         // slot 0 is the home cell itself (offset code 13 in 3D, 4 in 2D)
-        const int code = stencil_code(lane, G.nsten);
+        const int code = stencil_code(lane, nsten);
         const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = DIM == 3 ? code / 9 - 1 : 0;
         int x = cx + dx, y = cy + dy, z = cz + dz;
-        x += x < 0 ? G.n[0] : 0;
-        x -= x >= G.n[0] ? G.n[0] : 0;
-        y += y < 0 ? G.n[1] : 0;
-        y -= y >= G.n[1] ? G.n[1] : 0;
-        z += z < 0 ? G.n[2] : 0;
-        z -= z >= G.n[2] ? G.n[2] : 0;
-        const int nc = (z * G.n[1] + y) * G.n[0] + x;
+        x += x < 0 ? n0 : 0;
+        x -= x >= n0 ? n0 : 0;
+        y += y < 0 ? n1 : 0;
+        y -= y >= n1 ? n1 : 0;
+        z += z < 0 ? n2 : 0;
+        z -= z >= n2 ? n2 : 0;
+        const int nc = cell_base + (z * n1 + y) * n0 + x;
         st = in.cand_start[nc];
         cnt = in.cand_start[nc + 1] - st;
     }
@@ -126,31 +128,75 @@ __device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int 
         const int t = __shfl_up(incl, d);
         if (lane >= d) incl += t;
     }
-    if (lane < G.nsten) {
+    if (lane < nsten) {
         S.pre[lane + 1] = incl;
         S.start[lane] = st;
     }
     if (lane == 0) S.pre[0] = 0;
     wave_sync();
-    return uniform(__shfl(incl, G.nsten - 1));
+    return uniform(__shfl(incl, nsten - 1));
+}
+
+template <int DIM>
+__device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int tile, int lane,
+                                       StencilLds& S)
+{
+    return stencil<DIM>(in, G.n[0], G.n[1], G.n[2], G.nsten, 0, tile, lane, S);
 }
 
 // Candidate at flat stencil index k, relative to the home cell's centre.
 template <int DIM>
-__device__ __forceinline__ void fetch(const PairIn& in, const PairGeom& G, const StencilLds& S,
+__device__ __forceinline__ void fetch(const PairIn& in, int nsten, const StencilLds& S,
                                       const float4* off, int k, float& x, float& y, float& z,
                                       int& id)
 {
     int j = 0;
 #pragma unroll
     for (int step = 16; step > 0; step >>= 1)
-        if (j + step < G.nsten && S.pre[j + step] <= k) j += step;
+        if (j + step < nsten && S.pre[j + step] <= k) j += step;
     const float4 v = in.cand[S.start[j] + (k - S.pre[j])];
     const float4 o = off[j];
     x = v.x + o.x;
     y = v.y + o.y;
     z = DIM == 3 ? v.z + o.z : 0.f;
     id = __float_as_int(v.w);
+}
+
+template <int DIM>
+__device__ __forceinline__ void fetch(const PairIn& in, const PairGeom& G, const StencilLds& S,
+                                      const float4* off, int k, float& x, float& y, float& z,
+                                      int& id)
+{
+    fetch<DIM>(in, G.nsten, S, off, k, x, y, z, id);
+}
+
+// What the pair loops need of a frame's geometry (one frame, or the frame of
+// the current home cell in a batch).
+struct GeomView {
+    int n0, n1, n2, nsten;
+    int cell_base;  // first global cell id of the frame
+    float r2max;
+    int dot;        // expanded in/out test allowed
+};
+
+__device__ __forceinline__ GeomView view_of(const PairGeom& G)
+{
+    GeomView v;
+    v.n0 = G.n[0];
+    v.n1 = G.n[1];
+    v.n2 = G.n[2];
+    v.nsten = G.nsten;
+    v.cell_base = 0;
+    v.r2max = G.r2max;
+    v.dot = G.dot;
+    return v;
+}
+
+template <int DIM>
+__device__ __forceinline__ int stencil(const PairIn& in, const GeomView& V, int tile, int lane,
+                                       StencilLds& S)
+{
+    return stencil<DIM>(in, V.n0, V.n1, V.n2, V.nsten, V.cell_base, tile, lane, S);
 }
 
 // One query point in scalar registers, with the constants of both tests.
@@ -184,7 +230,7 @@ struct Slots {
     float cc[NS > 0 ? NS : 1];  // |c|^2
     int id[NS > 0 ? NS : 1];
 
-    __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
+    __device__ __forceinline__ void load(const PairIn& in, int nsten, const StencilLds& S,
                                          const float4* off, int k0, int C, int lane)
     {
 #pragma unroll
@@ -192,9 +238,14 @@ struct Slots {
             x[s] = y[s] = z[s] = kFar;
             id[s] = -1;
             const int k = k0 + s * kWave + lane;
-            if (k < C) fetch<DIM>(in, G, S, off, k, x[s], y[s], z[s], id[s]);
+            if (k < C) fetch<DIM>(in, nsten, S, off, k, x[s], y[s], z[s], id[s]);
             cc[s] = dist2<DIM>(x[s], y[s], z[s]);
         }
+    }
+    __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
+                                         const float4* off, int k0, int C, int lane)
+    {
+        load(in, G.nsten, S, off, k0, C, lane);
     }
     // the in/out test of slot s against q; identical in both passes
     template <bool DOT>

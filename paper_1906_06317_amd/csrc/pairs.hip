@@ -39,6 +39,7 @@ using namespace pair;
 constexpr int kHitCap = 384;  // hits buffered per wavefront between flushes
 constexpr int kRows = 64;     // rows buffered per wavefront
 constexpr int kFillSlots = 10;  // register slots of the fill pass (it needs more registers)
+constexpr int kMaxBatchLdsBins = 1024;  // per-wavefront histograms of a batch up to this size
 
 // ---------------------------------------------------------------------------
 // Pass 1: row lengths.
@@ -58,12 +59,12 @@ __device__ __forceinline__ int count_hits(const Slots<DIM, NS>& c, const Query& 
 }
 
 template <int DIM, int EXCL, int NS>
-__device__ __forceinline__ void count_tile(const PairIn& in, const PairGeom& G,
+__device__ __forceinline__ void count_tile(const PairIn& in, const GeomView& G,
                                            const StencilLds& S, const float4* off, int C, int q0,
                                            int q1, int lane, int32_t* __restrict__ counts)
 {
     Slots<DIM, NS> c;
-    c.load(in, G, S, off, 0, C, lane);
+    c.load(in, G.nsten, S, off, 0, C, lane);
     const float r2max = G.r2max;
     for (int c0 = q0; c0 < q1; c0 += kWave) {
         QueryChunk Q;
@@ -84,7 +85,7 @@ __device__ __forceinline__ void count_tile(const PairIn& in, const PairGeom& G,
 // Stencils too large for the register slots: candidate chunks of
 // kChunkSlots slots, each loaded once per 64 queries.
 template <int DIM, int EXCL>
-__device__ __forceinline__ void count_chunked(const PairIn& in, const PairGeom& G,
+__device__ __forceinline__ void count_chunked(const PairIn& in, const GeomView& G,
                                               const StencilLds& S, const float4* off, int C,
                                               int q0, int q1, int lane,
                                               int32_t* __restrict__ counts)
@@ -96,7 +97,7 @@ __device__ __forceinline__ void count_chunked(const PairIn& in, const PairGeom& 
         int cnt_v = EXCL == 1 ? -1 : 0;
         for (int k0 = 0; k0 < C; k0 += kChunkSlots * kWave) {
             Slots<DIM, kChunkSlots> c;
-            c.load(in, G, S, off, k0, C, lane);
+            c.load(in, G.nsten, S, off, k0, C, lane);
             for (int t = 0; t < Q.n; ++t) {
                 const Query q = Q.get<DIM>(t, r2max);
                 const int n = G.dot ? count_hits<DIM, EXCL, kChunkSlots, true>(c, q, r2max)
@@ -121,21 +122,22 @@ __global__ void __launch_bounds__(kBlock, 5) count_kernel(const PairIn in, const
         s_off[threadIdx.x] = make_float4(G.off[threadIdx.x][0], G.off[threadIdx.x][1],
                                          G.off[threadIdx.x][2], 0.f);
     __syncthreads();
+    const GeomView V = view_of(G);
     int t0, t1;
     wave_tiles(G.ncells, wv, t0, t1);
     for (int tile = t0; tile < t1; ++tile) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, G, tile, lane, S);
+        const int C = stencil<DIM>(in, V, tile, lane, S);
         const int ns = (C + kWave - 1) / kWave;
         switch (ns) {
 #define PPA_CASE(N) \
-    case N: count_tile<DIM, EXCL, N>(in, G, S, s_off, C, q0, q1, lane, counts); break;
+    case N: count_tile<DIM, EXCL, N>(in, V, S, s_off, C, q0, q1, lane, counts); break;
             PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
             PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
 #undef PPA_CASE
-        default: count_chunked<DIM, EXCL>(in, G, S, s_off, C, q0, q1, lane, counts);
+        default: count_chunked<DIM, EXCL>(in, V, S, s_off, C, q0, q1, lane, counts);
         }
     }
 }
@@ -182,7 +184,9 @@ template <int DIM, int EXCL, bool NL, bool HIST>
 struct Filler {
     FillLds<NL>& W;
     const FillOut O;
-    unsigned* hist_lds;  // NULL: bin straight into O.hist
+    unsigned* hist_lds;  // NULL: bin straight into ghist
+    unsigned long long* ghist;  // the histogram in global memory (the frame's, in a batch)
+    int id_base;  // subtracted from point indices written to the list (frame-local indices)
     int lane;
     int nh;     // hits buffered
     int nrows;  // rows buffered
@@ -190,7 +194,8 @@ struct Filler {
     bool over;
 
     __device__ Filler(FillLds<NL>& w, const FillOut& o, unsigned* h, int l)
-        : W(w), O(o), hist_lds(h), lane(l), nh(0), nrows(0), selfs(0), over(false)
+        : W(w), O(o), hist_lds(h), ghist(o.hist), id_base(0), lane(l), nh(0), nrows(0), selfs(0),
+          over(false)
     {
     }
 
@@ -202,13 +207,13 @@ struct Filler {
             if (hist_lds)
                 atomicAdd(&hist_lds[b], 1u);
             else
-                atomicAdd(&O.hist[b], 1ull);
+                atomicAdd(&ghist[b], 1ull);
         }
     }
     __device__ __forceinline__ void emit(long long dst, int id, float r)
     {
         if (dst < O.capacity) {
-            O.point_idx[dst] = id;
+            O.point_idx[dst] = id - id_base;
             if (O.dist) O.dist[dst] = r;
         } else {
             over = true;
@@ -315,13 +320,13 @@ struct Filler {
 };
 
 template <int DIM, int EXCL, bool NL, bool HIST, int NS>
-__device__ __forceinline__ void fill_tile(const PairIn& in, const PairGeom& G, const StencilLds& S,
+__device__ __forceinline__ void fill_tile(const PairIn& in, const GeomView& G, const StencilLds& S,
                                           const float4* off, int C, int q0, int q1,
                                           Filler<DIM, EXCL, NL, HIST>& F)
 {
     const int lane = F.lane;
     Slots<DIM, NS> c;
-    c.load(in, G, S, off, 0, C, lane);
+    c.load(in, G.nsten, S, off, 0, C, lane);
     const float r2max = G.r2max;
     for (int c0 = q0; c0 < q1; c0 += kWave) {
         QueryChunk Q;
@@ -374,7 +379,7 @@ __device__ __forceinline__ void fill_tile(const PairIn& in, const PairGeom& G, c
 }
 
 template <int DIM, int EXCL, bool NL, bool HIST>
-__device__ __forceinline__ void fill_chunked(const PairIn& in, const PairGeom& G,
+__device__ __forceinline__ void fill_chunked(const PairIn& in, const GeomView& G,
                                              const StencilLds& S, const float4* off, int C,
                                              int q0, int q1, Filler<DIM, EXCL, NL, HIST>& F)
 {
@@ -388,7 +393,7 @@ __device__ __forceinline__ void fill_chunked(const PairIn& in, const PairGeom& G
         int w_v = 0;  // entries written so far, per query
         for (int k0 = 0; k0 < C; k0 += kChunkSlots * kWave) {
             Slots<DIM, kChunkSlots> c;
-            c.load(in, G, S, off, k0, C, lane);
+            c.load(in, G.nsten, S, off, k0, C, lane);
             for (int t = 0; t < Q.n; ++t) {
                 const Query q = Q.get<DIM>(t, r2max);
                 const long long rbase = NL ? lane_of64(rb_v, t) : 0;
@@ -426,22 +431,23 @@ __global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const 
         wave_sync();
     }
     Filler<DIM, EXCL, NL, HIST> F(s_w[wv], O, lds_hist ? s_hist : nullptr, lane);
+    const GeomView V = view_of(G);
     int t0, t1;
     wave_tiles(G.ncells, wv, t0, t1);
     for (int tile = t0; tile < t1; ++tile) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, G, tile, lane, S);
+        const int C = stencil<DIM>(in, V, tile, lane, S);
         const int ns = (C + kWave - 1) / kWave;
         switch (ns) {
 #define PPA_CASE(N) \
-    case N: fill_tile<DIM, EXCL, NL, HIST, N>(in, G, S, s_off, C, q0, q1, F); break;
+    case N: fill_tile<DIM, EXCL, NL, HIST, N>(in, V, S, s_off, C, q0, q1, F); break;
             PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
             PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
 #undef PPA_CASE
             static_assert(kFillSlots == 10, "the cases above cover 0..kFillSlots");
-        default: fill_chunked<DIM, EXCL, NL, HIST>(in, G, S, s_off, C, q0, q1, F);
+        default: fill_chunked<DIM, EXCL, NL, HIST>(in, V, S, s_off, C, q0, q1, F);
         }
     }
     if (F.nh > 0) F.flush();
@@ -459,6 +465,157 @@ __global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const 
             const unsigned v = s_hist[b];
             if (v) atomicAdd(&O.hist[b], (unsigned long long)v);
         }
+}
+
+// ---------------------------------------------------------------------------
+// Batch: the same passes over the cells of many frames at once.  The home
+// cells of all frames form one global range; a wavefront walks its
+// contiguous share of it and switches geometry (grid, stencil offsets,
+// frame-local point indices, the frame's histogram) when its cells cross
+// into the next frame, which happens at most a few times per wavefront.
+// ---------------------------------------------------------------------------
+// Frame of global cell `tile`: the last f with cell_base[f] <= tile.
+__device__ __forceinline__ int frame_of(const BatchGeom& B, int tile)
+{
+    int lo = 0, hi = B.nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.cell_base[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return uniform(lo);
+}
+
+// Loads frame f's geometry: the view in scalar registers, the stencil
+// offsets into this wavefront's LDS.
+__device__ __forceinline__ GeomView load_frame(const BatchGeom& B, int f, float4* off, int lane)
+{
+    const FrameInfo& F = B.frames[f];
+    GeomView v;
+    v.n0 = uniform(F.box.ni[0]);
+    v.n1 = uniform(F.box.ni[1]);
+    v.n2 = uniform(F.box.ni[2]);
+    v.nsten = uniform(F.nsten);
+    v.cell_base = uniform(F.cell_base);
+    v.r2max = B.r2max;
+    v.dot = uniform(F.dot);
+    if (lane < 27) off[lane] = make_float4(F.off[lane][0], F.off[lane][1], F.off[lane][2], 0.f);
+    wave_sync();
+    return v;
+}
+
+template <int DIM, int EXCL>
+__global__ void __launch_bounds__(kBlock, 5) count_batch_kernel(const PairIn in, const BatchGeom B,
+                                                             int32_t* __restrict__ counts)
+{
+    __shared__ float4 s_off[kWavesPerBlock][27];
+    __shared__ StencilLds s_st[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = uniform(threadIdx.x / kWave);
+    StencilLds& S = s_st[wv];
+    float4* off = s_off[wv];
+    int t0, t1;
+    wave_tiles(B.ncells, wv, t0, t1);
+    if (t0 >= t1) return;
+    int f = frame_of(B, t0);
+    GeomView V = load_frame(B, f, off, lane);
+    int next = B.cell_base[f + 1];
+    for (int tile = t0; tile < t1; ++tile) {
+        if (tile >= next) {
+            while (B.cell_base[f + 1] <= tile) ++f;
+            f = uniform(f);
+            V = load_frame(B, f, off, lane);
+            next = B.cell_base[f + 1];
+        }
+        const int q0 = in.q_start[tile];
+        const int q1 = in.q_start[tile + 1];
+        if (q0 == q1) continue;
+        const int C = stencil<DIM>(in, V, tile, lane, S);
+        const int ns = (C + kWave - 1) / kWave;
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: count_tile<DIM, EXCL, N>(in, V, S, off, C, q0, q1, lane, counts); break;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
+#undef PPA_CASE
+        default: count_chunked<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, counts);
+        }
+    }
+}
+
+// Adds this wavefront's LDS histogram into the global one and clears it.
+__device__ __forceinline__ void merge_wave_hist(unsigned* h, unsigned long long* g, int bins,
+                                                int lane)
+{
+    wave_sync();
+    for (int b = lane; b < bins; b += kWave) {
+        const unsigned v = h[b];
+        if (v) {
+            atomicAdd(&g[b], (unsigned long long)v);
+            h[b] = 0u;
+        }
+    }
+    wave_sync();
+}
+
+// NeighborList and per-frame RDF (histograms [nframes][bins]) of a batch.
+template <int DIM, int EXCL>
+__global__ void __launch_bounds__(kBlock, 4) fill_batch_kernel(const PairIn in, const BatchGeom B,
+                                                            const FillOut O)
+{
+    extern __shared__ unsigned s_dyn[];  // one histogram per wavefront when bins are few
+    __shared__ float4 s_off[kWavesPerBlock][27];
+    __shared__ FillLds<true> s_w[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = uniform(threadIdx.x / kWave);
+    StencilLds& S = s_w[wv].st;
+    float4* off = s_off[wv];
+    const bool lds_hist = O.bins <= kMaxBatchLdsBins;
+    unsigned* h = lds_hist ? s_dyn + (size_t)wv * O.bins : nullptr;
+    if (lds_hist)
+        for (int b = lane; b < O.bins; b += kWave) h[b] = 0u;
+    if (lane < kHitCap / 64) s_w[wv].starts[lane] = 0ull;
+    wave_sync();
+    int t0, t1;
+    wave_tiles(B.ncells, wv, t0, t1);
+    if (t0 >= t1) return;
+    Filler<DIM, EXCL, true, true> F(s_w[wv], O, h, lane);
+    int f = frame_of(B, t0);
+    GeomView V = load_frame(B, f, off, lane);
+    F.ghist = O.hist + (size_t)f * O.bins;
+    F.id_base = uniform(B.frames[f].point_base);
+    int next = B.cell_base[f + 1];
+    for (int tile = t0; tile < t1; ++tile) {
+        if (tile >= next) {
+            // buffered hits belong to the old frame: write them and its bins first
+            if (F.nh > 0) F.flush();
+            if (lds_hist) merge_wave_hist(h, F.ghist, O.bins, lane);
+            while (B.cell_base[f + 1] <= tile) ++f;
+            f = uniform(f);
+            V = load_frame(B, f, off, lane);
+            F.ghist = O.hist + (size_t)f * O.bins;
+            F.id_base = uniform(B.frames[f].point_base);
+            next = B.cell_base[f + 1];
+        }
+        const int q0 = in.q_start[tile];
+        const int q1 = in.q_start[tile + 1];
+        if (q0 == q1) continue;
+        const int C = stencil<DIM>(in, V, tile, lane, S);
+        const int ns = (C + kWave - 1) / kWave;
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: fill_tile<DIM, EXCL, true, true, N>(in, V, S, off, C, q0, q1, F); break;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
+#undef PPA_CASE
+        default: fill_chunked<DIM, EXCL, true, true>(in, V, S, off, C, q0, q1, F);
+        }
+    }
+    if (F.nh > 0) F.flush();
+    if (lds_hist) merge_wave_hist(h, F.ghist, O.bins, lane);
+    if (__ballot(F.over) && lane == 0) atomicOr(O.status, kStatusCapacity);
 }
 
 __global__ void __launch_bounds__(256) hist_from_dist_kernel(const float* __restrict__ dist,
@@ -534,6 +691,77 @@ void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s)
         if (excl == 1) PPA_COUNT(2, 1); else if (excl == 2) PPA_COUNT(2, 2); else PPA_COUNT(2, 0);
     }
 #undef PPA_COUNT
+}
+
+static int capped(int blocks, int blocks_cap)
+{
+    if (blocks_cap <= 0) return blocks;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                  ? prop.multiProcessorCount
+                  : 256;
+    }
+    const int cap = cus * blocks_cap;
+    return blocks < cap ? blocks : cap;
+}
+
+template <int DIM, int EXCL>
+static void count_batch_t(const PairIn& in, const BatchGeom& b, int32_t* counts, int blocks_cap,
+                          hipStream_t s)
+{
+    auto k = count_batch_kernel<DIM, EXCL>;
+    const int blocks = capped(resident_blocks(k, 0, b.ncells), blocks_cap);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), 0, s, in, b, counts);
+}
+
+template <int DIM, int EXCL>
+static void fill_batch_t(const PairIn& in, const BatchGeom& b, const FillOut& o, int blocks_cap,
+                         hipStream_t s)
+{
+    const size_t lds =
+        o.bins <= kMaxBatchLdsBins ? sizeof(unsigned) * (size_t)o.bins * kWavesPerBlock : 0;
+    auto k = fill_batch_kernel<DIM, EXCL>;
+    const int blocks = capped(resident_blocks(k, lds, b.ncells), blocks_cap);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), lds, s, in, b, o);
+}
+
+void launch_count_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
+                        hipStream_t s)
+{
+    const PairIn in = make_in(a);
+    if (dim == 3) {
+        if (excl) count_batch_t<3, 1>(in, b, a.counts, blocks_cap, s);
+        else count_batch_t<3, 0>(in, b, a.counts, blocks_cap, s);
+    } else {
+        if (excl) count_batch_t<2, 1>(in, b, a.counts, blocks_cap, s);
+        else count_batch_t<2, 0>(in, b, a.counts, blocks_cap, s);
+    }
+}
+
+void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
+                       hipStream_t s)
+{
+    const PairIn in = make_in(a);
+    FillOut o;
+    o.offsets = a.offsets;
+    o.point_idx = a.point_idx;
+    o.dist = a.dist;
+    o.capacity = a.capacity;
+    o.status = a.status;
+    o.hist = a.hist;
+    o.bins = a.bins;
+    o.r_min = a.r_min;
+    o.inv_dr = a.inv_dr;
+    if (dim == 3) {
+        if (excl) fill_batch_t<3, 1>(in, b, o, blocks_cap, s);
+        else fill_batch_t<3, 0>(in, b, o, blocks_cap, s);
+    } else {
+        if (excl) fill_batch_t<2, 1>(in, b, o, blocks_cap, s);
+        else fill_batch_t<2, 0>(in, b, o, blocks_cap, s);
+    }
 }
 
 void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s)

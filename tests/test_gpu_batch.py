@@ -1,0 +1,191 @@
+"""GPU parity: batched analysis of many frames (one cell list, one sequence
+of launches) against the oracle frame by frame, against per-frame calls,
+and replayed from a HIP graph."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_06317_amd import workloads
+from tests.parity import check_hist, check_rows
+
+pytestmark = pytest.mark.gpu
+
+R_MAX, BINS = 2.5, 128
+
+
+@pytest.fixture(scope="module")
+def ppa():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    import paper_1906_06317_amd as m
+    m.lib()
+    return m
+
+
+class _FrameNL:
+    """Rows of one frame cut out of the batch's NeighborList."""
+
+    def __init__(self, nl, a, b):
+        off = nl.offsets.cpu().numpy()
+        lo, hi = int(off[a]), int(off[b])
+        import torch
+        self.offsets = torch.as_tensor(off[a:b + 1] - lo)
+        self.counts = nl.counts[a:b].cpu()
+        self.point_idx = nl.point_idx[lo:hi].cpu()
+        self.dist = nl.dist[lo:hi].cpu()
+
+
+def _frames(seed, count, n_lo, n_hi, dim=3):
+    fr = workloads.trajectory(seed=seed, frames=count, n_lo=n_lo, n_hi=n_hi)
+    if dim == 2:
+        out = []
+        for k, f in enumerate(fr):
+            s = workloads.uniform(f.points.shape[0], 0.8, seed=seed * 100 + k, dim=2,
+                                  tilt=(f.tilt[0], 0.0, 0.0))
+            out.append(s)
+        fr = out
+    return fr
+
+
+def _plan(ppa, frames, **kw):
+    boxes = [ppa.Box(f.L, f.tilt, f.dim) for f in frames]
+    sizes = [f.points.shape[0] for f in frames]
+    return ppa.BatchPlan(boxes, sizes, BINS, R_MAX, **kw), np.concatenate([f.points for f in frames])
+
+
+def _check_against_oracle(frames, hist, nl, pb, which=None):
+    hist = hist.cpu().numpy()
+    for f in (range(len(frames)) if which is None else which):
+        s = frames[f]
+        ob = oracle.make_box(s.L, s.tilt, s.dim)
+        lo, hi, _ = oracle.rdf_counts(ob, s.points, BINS, R_MAX)
+        check_hist(hist[f], lo, hi)
+        ref = oracle.ball_query(ob, s.points, R_MAX)
+        check_rows(_FrameNL(nl, pb[f], pb[f + 1]), ref, range(s.points.shape[0]), R_MAX)
+
+
+def test_small_trajectory_against_oracle_and_per_frame_calls(ppa):
+    frames = _frames(11, 12, 1500, 6000)
+    plan, pts = _plan(ppa, frames)
+    assert plan.config()["chosen"] == 0
+    hist, nl = plan.run(pts)
+    _check_against_oracle(frames, hist, nl, plan.offsets_host)
+    # configuration 0 uses the per-frame grid: identical to per-frame calls
+    h = hist.cpu().numpy()
+    off = nl.offsets.cpu().numpy()
+    pidx = nl.point_idx.cpu().numpy()
+    pb = plan.offsets_host
+    for f, s in enumerate(frames):
+        box = ppa.Box(s.L, s.tilt, s.dim)
+        c, fnl = ppa.rdf_counts(box, s.points, BINS, R_MAX, neighbor_list=True)
+        np.testing.assert_array_equal(h[f], c.cpu().numpy())
+        fo = fnl.offsets.cpu().numpy()
+        np.testing.assert_array_equal(off[pb[f]:pb[f + 1] + 1] - off[pb[f]], fo)
+        np.testing.assert_array_equal(pidx[off[pb[f]]:off[pb[f + 1]]], fnl.point_idx.cpu().numpy())
+
+
+def test_every_configuration_and_the_autotuner(ppa):
+    frames = _frames(12, 6, 2000, 8000)
+    plan, pts = _plan(ppa, frames)
+    n = plan.config()["n_configs"]
+    assert n >= 4
+    for c in range(n):
+        plan.config(c)
+        hist, nl = plan.run(pts)
+        _check_against_oracle(frames, hist, nl, plan.offsets_host, which=[0, len(frames) - 1])
+        h = hist.cpu().numpy()
+        for f, s in enumerate(frames):
+            lo, hi, _ = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), s.points, BINS, R_MAX)
+            check_hist(h[f], lo, hi)
+    ms, cfg = plan.autotune(pts, reps=2)
+    assert len(ms) == n and all(t > 0 for t in ms)
+    assert cfg["chosen"] == int(np.argmin(ms))
+    hist, nl = plan.run(pts)
+    _check_against_oracle(frames, hist, nl, plan.offsets_host, which=[1])
+
+
+def test_graph_replays(ppa):
+    import torch
+    frames = _frames(13, 8, 1000, 5000)
+    plan, pts = _plan(ppa, frames)
+    p = torch.as_tensor(pts).cuda()
+    h1, nl1 = plan.run(p)
+    ref_idx = nl1.point_idx.cpu().numpy().copy()
+    ref_h = h1.cpu().numpy().copy()
+    hist = torch.zeros((len(frames), BINS), dtype=torch.int64, device="cuda")
+    launch = plan.graph(p, hist)
+    for k in range(3):
+        launch()
+        torch.cuda.synchronize()
+        assert plan.ws.status() == 0
+        np.testing.assert_array_equal(hist.cpu().numpy(), (k + 1) * ref_h)
+        np.testing.assert_array_equal(plan.neighbor_list().point_idx.cpu().numpy(), ref_idx)
+        # eager work between replays
+        plan.run(p)
+
+
+def test_tiny_and_empty_frames_and_2d(ppa):
+    rng = np.random.default_rng(3)
+    frames = _frames(14, 5, 1000, 3000)
+    L = frames[0].L
+    empty = workloads.System(L, (0.0, 0.0, 0.0), 3, np.zeros((0, 3), np.float32))
+    one = workloads.System(L, (0.1, 0.0, 0.0), 3, rng.uniform(-2, 2, (1, 3)).astype(np.float32))
+    frames = [frames[0], empty, one, frames[1], empty, frames[2]]
+    plan, pts = _plan(ppa, frames)
+    hist, nl = plan.run(pts)
+    _check_against_oracle(frames, hist, nl, plan.offsets_host)
+    assert hist[1].sum().item() == 0 and hist[2].sum().item() == 0
+    f2 = _frames(15, 4, 1500, 4000, dim=2)
+    plan2, pts2 = _plan(ppa, f2)
+    hist2, nl2 = plan2.run(pts2)
+    _check_against_oracle(f2, hist2, nl2, plan2.offsets_host)
+
+
+def test_plan_errors(ppa):
+    small = ppa.Box.cube(4.0)  # half width 2 < r_max
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.BatchPlan([ppa.Box.cube(20.0), small], [10, 10], BINS, R_MAX)
+    assert e.value.code == ppa.PPA_ERANGE and "frame 1" in str(e.value)
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.BatchPlan([ppa.Box.cube(20.0), ppa.Box.cube(20.0, dim=2)], [10, 10], BINS, R_MAX)
+    assert e.value.code == ppa.PPA_EINVAL
+
+
+def test_full_trajectory(ppa):
+    """The 256-frame trajectory (N_f log-uniform in [1e3, 2e5], own triclinic
+    boxes): autotuned batch; small frames against the oracle, the largest
+    frame's sampled rows against the oracle, and every frame's histogram
+    against per-frame calls."""
+    import torch
+    frames = workloads.trajectory()
+    plan, pts = _plan(ppa, frames)
+    p = torch.as_tensor(pts).cuda()
+    plan.autotune(p, reps=1)
+    hist, nl = plan.run(p)
+    sizes = np.array([f.points.shape[0] for f in frames])
+    small = list(np.argsort(sizes)[:4])
+    _check_against_oracle(frames, hist, nl, plan.offsets_host, which=small)
+    big = int(np.argmax(sizes))
+    s = frames[big]
+    pb = plan.offsets_host
+    rows = np.sort(np.random.default_rng(8).choice(s.points.shape[0], 100, replace=False))
+    ob = oracle.make_box(s.L, s.tilt, s.dim)
+    csr_off, csr_idx, csr_r2 = [0], [], []
+    for q in rows:
+        o, i, r = oracle.ball_query(ob, s.points, R_MAX, query_points=s.points[q:q + 1],
+                                    exclude_ii=False)
+        keep = i != q
+        csr_idx.append(i[keep])
+        csr_r2.append(r[keep])
+        csr_off.append(csr_off[-1] + int(keep.sum()))
+    check_rows(_FrameNL(nl, pb[big], pb[big + 1]),
+               (np.array(csr_off), np.concatenate(csr_idx), np.concatenate(csr_r2)), rows, R_MAX)
+    h = hist.cpu().numpy()
+    total = 0
+    for f, s in enumerate(frames):
+        c = ppa.rdf_counts(ppa.Box(s.L, s.tilt, s.dim), s.points, BINS, R_MAX).cpu().numpy()
+        total += int(c.sum())
+        # a different cell width may decide pairs in the rounding band
+        # differently: at most a handful per frame
+        assert np.abs(h[f] - c).sum() <= max(4, int(1e-6 * c.sum()))
+    assert abs(nl.n_pairs - total) <= 256 * 4
