@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: periodic ball query + RDF at N = 1,048,576 on one MI355X.
+"""Benchmark: periodic neighbour queries and pair histograms on one MI355X.
 
-Workload: 64^3 FCC cells (N = 1,048,576) with Gaussian noise 0.05 a,
-a = 4^(1/3) (density 1), in a triclinic box with tilts (0.5, 0.2, 0.1);
-ball query r_max = 2.5 into a NeighborList (point index + distance per
-pair) with a 256-bin RDF on [0, 2.5) binned in the same pass.
+Headline step (the large configuration): 64^3 FCC cells (N = 1,048,576)
+with Gaussian noise 0.05 a, a = 4^(1/3) (density 1), in a triclinic box
+with tilts (0.5, 0.2, 0.1).  One step, from positions resident in HBM:
+cell-list build, the ball query r_max = 2.5 writing the NeighborList (point
+index + distance per pair) with the 256-bin RDF on [0, 2.5) binned in the
+same pass, and the k = 12 nearest-neighbour query (its own cell list).
+`value` counts the ordered ball pairs found, listed and binned per second
+of the whole step.  The fill kernel (the dominant one) is timed with HIP
+events on its stream inside the timed region for the roofline entry.
 
-A step is one full pass from positions resident in HBM: cell-list build
-(cell index, counting sort, scans), the ball query writing the list, and the
-RDF histogram.  `value` counts ordered pairs found (and written, and binned)
-per second.  The dominant kernel (the pair kernel) is timed with HIP events
-on its own stream inside the timed region for the roofline entry.
+The other hot-path steps are measured on their own workloads and reported
+under "rows": the 2D PMFT (N = 262,144 fluid, 200 x 200 bins), the batched
+trajectory (256 frames of uneven size, each with its own box; one HIP-graph
+launch against a loop of per-frame calls) and the Gaussian-smoothed RDF
+forward and adjoint (N = 131,072).
 
-The FP64 oracle is timed on the host on a bounded sample of query rows
-(cpu_baseline); it is the brute-force checker, not a tuned CPU code.
+The FP64 oracle is timed on the host on a bounded sample of query rows of
+the headline system (cpu_baseline); it is the brute-force checker, not a
+tuned CPU code.
 """
 import argparse
 import ctypes
@@ -37,20 +43,55 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="headline step only")
     return ap.parse_args()
 
 
-def hip_runtime():
-    import torch  # noqa: F401  (loads the process's HIP runtime first)
-    L = ctypes.CDLL("libamdhip64.so.7")
-    L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
-    L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
-                                      ctypes.c_void_p]
-    L.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    return L
+class Hip:
+    """HIP events through the process's HIP runtime (the one torch loaded)."""
+
+    def __init__(self):
+        import torch  # noqa: F401
+        L = ctypes.CDLL("libamdhip64.so.7")
+        L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                          ctypes.c_void_p]
+        L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.L = L
+
+    def events(self, n):
+        out = [ctypes.c_void_p() for _ in range(n)]
+        for e in out:
+            assert self.L.hipEventCreate(ctypes.byref(e)) == 0
+        return out
+
+    def ms(self, a, b):
+        f = ctypes.c_float()
+        assert self.L.hipEventElapsedTime(ctypes.byref(f), a, b) == 0
+        return f.value
+
+    def destroy(self, evs):
+        for e in evs:
+            self.L.hipEventDestroy(e)
 
 
-def cpu_baseline(sysm, n_pairs_total, target_s):
+def timed(fn, reps, warmup=1):
+    """Mean ms per call of fn() on the current stream (torch events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def cpu_baseline(sysm, target_s):
     import numpy as np
 
     import oracle
@@ -64,10 +105,11 @@ def cpu_baseline(sysm, n_pairs_total, target_s):
         t = time.perf_counter()
         # per query row: the neighbour list (count + fill) and the RDF pass
         _, idx, _ = oracle.ball_query(ob, sysm.points, 2.5, query_points=q, exclude_ii=False)
-        lo, hi, _ = oracle.rdf_counts(ob, sysm.points, 256, 2.5, query_points=q, exclude_ii=False)
+        oracle.rdf_counts(ob, sysm.points, 256, 2.5, query_points=q, exclude_ii=False)
         dt = time.perf_counter() - t
         return dt, int(idx.shape[0]) - nq  # drop each row's self pair at r = 0
 
+    run(32)  # thread start-up
     dt, _ = run(128)
     nq = int(min(n, max(128, 128 * target_s / max(dt, 1e-3))))
     dt, pairs = run(nq)
@@ -77,24 +119,15 @@ def cpu_baseline(sysm, n_pairs_total, target_s):
                       f"all points, FP64), ball list + RDF, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              f"(asked for --gpus {args.gpus})", file=sys.stderr)
-        sys.exit(2)
+def headline(args, ppa, hip):
     import numpy as np
     import torch
 
-    import paper_1906_06317_amd as ppa
     from paper_1906_06317_amd import workloads
-
-    torch.cuda.set_device(0)
-    hip = hip_runtime()
     L = ppa.lib()
     sysm = workloads.large_fcc()
     n = sysm.points.shape[0]
-    r_max, bins = 2.5, 256
+    r_max, bins, k = 2.5, 256, 12
     box = ppa.Box(sysm.L, sysm.tilt, sysm.dim)
     pts = torch.as_tensor(sysm.points).cuda()
 
@@ -106,69 +139,76 @@ def main():
 
     ws = ppa.Workspace()
     wptr, wlen = ws.get(ppa.workspace_bytes(box, n, 0, r_max, ppa.PPA_WS_NLIST))
+    wsk = ppa.Workspace()
+    kptr, klen = wsk.get(ppa.knn_workspace_bytes(box, n, 0, k))
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
     rowc = torch.empty(n, dtype=torch.int32, device="cuda")
     pidx = torch.empty(P, dtype=torch.int32, device="cuda")
     dist = torch.empty(P, dtype=torch.float32, device="cuda")
     npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
     hist = torch.zeros(bins, dtype=torch.int64, device="cuda")
+    koff = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    kidx = torch.empty(n * k, dtype=torch.int32, device="cuda")
+    kdist = torch.empty(n * k, dtype=torch.float32, device="cuda")
+    knp = torch.zeros(1, dtype=torch.int64, device="cuda")
     cb = box.c()
-    stream = torch.cuda.current_stream()
-    sptr = ctypes.c_void_p(stream.cuda_stream)
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     p = lambda t: ctypes.c_void_p(t.data_ptr())
 
-    def step():
+    def step(ev=None):
+        if ev:
+            L.ppa_profile_next(ev[0], ev[1], ev[2], ev[3])
         rc = L.ppa_rdf(ctypes.byref(cb), p(pts), n, None, n, bins, 0.0, r_max, 1, 0, wptr, wlen,
                        p(hist), p(offsets), p(rowc), p(pidx), p(dist), P, p(npairs), sptr)
+        if rc != 0:
+            raise RuntimeError(L.ppa_last_error().decode())
+        if ev:
+            L.ppa_profile_next(None, None, ev[4], ev[5])
+        rc = L.ppa_query_knn(ctypes.byref(cb), p(pts), n, None, n, k, 0.0, 1, 0, kptr, klen,
+                             p(koff), None, p(kidx), p(kdist), p(knp), sptr)
         if rc != 0:
             raise RuntimeError(L.ppa_last_error().decode())
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    if ws.status() != 0:
+    if ws.status() != 0 or wsk.status() != 0:
         raise RuntimeError("device status after warmup: " + L.ppa_last_error().decode())
 
-    ev = []
-    for _ in range(args.steps):
-        e4 = [ctypes.c_void_p() for _ in range(4)]
-        for e in e4:
-            assert hip.hipEventCreate(ctypes.byref(e)) == 0
-        ev.append(e4)
+    ev = [hip.events(6) for _ in range(args.steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
     for i in range(args.steps):
-        L.ppa_profile_next(*ev[i])
-        step()
+        step(ev[i])
     t1.record()
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
-    count_ms, fill_ms = [], []
-    for e4 in ev:
-        f = ctypes.c_float()
-        assert hip.hipEventElapsedTime(ctypes.byref(f), e4[0], e4[1]) == 0
-        count_ms.append(f.value)
-        assert hip.hipEventElapsedTime(ctypes.byref(f), e4[2], e4[3]) == 0
-        fill_ms.append(f.value)
-        for e in e4:
-            hip.hipEventDestroy(e)
-    st = ws.status()
-    if st != 0:
+    count_ms = float(np.mean([hip.ms(e[0], e[1]) for e in ev]))
+    fill_ms = float(np.mean([hip.ms(e[2], e[3]) for e in ev]))
+    knn_ms = float(np.mean([hip.ms(e[4], e[5]) for e in ev]))
+    for e in ev:
+        hip.destroy(e)
+    if ws.status() != 0 or wsk.status() != 0:
         raise RuntimeError("device status: " + L.ppa_last_error().decode())
     # the histogram accumulates over calls: every step must add the same counts
     h = hist.cpu().numpy()
     assert np.array_equal(h, hist1 * (args.warmup + args.steps)), "histogram drifted across steps"
-    assert int(npairs.item()) == P
+    assert int(npairs.item()) == P and int(knp.item()) == n * k
 
-    kernel_ms = float(np.mean(fill_ms))
+    # ball + RDF alone, for the row table
+    def ball_only():
+        L.ppa_rdf(ctypes.byref(cb), p(pts), n, None, n, bins, 0.0, r_max, 1, 0, wptr, wlen,
+                  p(hist), p(offsets), p(rowc), p(pidx), p(dist), P, p(npairs), sptr)
+    ball_ms = timed(ball_only, max(5, args.steps // 2))
+
     # algorithmic bytes of the fill kernel per launch: positions read (12 B per
     # point), row offsets read (8 B per query), neighbour list written (4 B
     # index + 4 B distance per pair), histogram (8 B per bin)
     alg_bytes = 12 * n + 8 * n + 8 * P + 8 * bins
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    out = {
+    achieved = alg_bytes / (fill_ms * 1e-3) / 1e9
+    line = {
         "metric": "pair evaluations/s for periodic ball query+RDF at N=1M; batched vs per-frame",
         "value": P / (ms_step * 1e-3),
         "unit": "pairs/s",
@@ -182,19 +222,204 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "noisy FCC N=1,048,576 (a=4^(1/3), sigma=0.05a), triclinic box "
-                               "tilts (0.5,0.2,0.1); ball r_max=2.5 -> NeighborList + RDF 256 bins",
-                   "n_points": n, "r_max": r_max, "bins": bins, "n_pairs": P,
+                               "tilts (0.5,0.2,0.1); ball r_max=2.5 -> NeighborList + RDF 256 bins, "
+                               "plus k=12 nearest query",
+                   "n_points": n, "r_max": r_max, "bins": bins, "k": k, "n_pairs": P,
                    "rows": "CSR in query order (count, scan, fill)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "fill_kernel (ball list + RDF)", "kernel_ms": kernel_ms,
-                     "algorithmic_bytes": alg_bytes,
-                     "count_kernel_ms": float(np.mean(count_ms)),
-                     "step_effective_GBps": (12 * n + 8 * P + 8 * n + 8 * bins) / (ms_step * 1e-3) / 1e9},
+                     "kernel": "fill_kernel (ball list + RDF)", "kernel_ms": fill_ms,
+                     "algorithmic_bytes": alg_bytes, "count_kernel_ms": count_ms},
     }
+    rows = {
+        "ball_rdf": {"ms": ball_ms, "pairs_per_s": P / (ball_ms * 1e-3),
+                     "note": "cell build + count + scan + fill with fused RDF"},
+        "knn": {"workload": "same system, k=12 (own cell list)", "ms_in_step": None,
+                "select_kernels_ms": knn_ms, "pairs": n * k},
+    }
+    knn_call = timed(lambda: L.ppa_query_knn(ctypes.byref(cb), p(pts), n, None, n, k, 0.0, 1, 0,
+                                             kptr, klen, p(koff), None, p(kidx), p(kdist), p(knp),
+                                             sptr), 10)
+    rows["knn"]["ms_in_step"] = knn_call
+    rows["knn"]["pairs_per_s"] = n * k / (knn_call * 1e-3)
+    return line, rows, sysm
+
+
+def row_pmft(ppa, hip):
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s = workloads.fluid_2d()
+    n = s.points.shape[0]
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    th = torch.as_tensor(s.theta).cuda()
+    ws = ppa.Workspace()
+    wptr, wlen = ws.get(ppa.pmft2d_workspace_bytes(box, n, 0, 200, 200, 3.0, 3.0, 3.0))
+    counts = torch.zeros(200 * 200, dtype=torch.int32, device="cuda")
+    cb = box.c()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    evs = []
+
+    def call():
+        e = hip.events(2)
+        evs.append(e)
+        L.ppa_profile_next(None, None, e[0], e[1])
+        rc = L.ppa_pmft2d(ctypes.byref(cb), p(pts), n, None, p(th), n, 200, 200, 3.0, 3.0, 3.0, 1,
+                          0, wptr, wlen, p(counts), sptr)
+        if rc != 0:
+            raise RuntimeError(L.ppa_last_error().decode())
+    ms = timed(call, 10, warmup=2)
+    kern = float(np.mean([hip.ms(e[0], e[1]) for e in evs[2:]]))
+    for e in evs:
+        hip.destroy(e)
+    if ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+    pairs = int(counts.to(torch.int64).sum().item()) // 12
+    return {"workload": "2D fluid N=262,144, density 0.7, r_max=3, 200x200 bins on [-3,3)^2",
+            "ms": ms, "binning_kernels_ms": kern, "pairs": pairs,
+            "pairs_per_s": pairs / (ms * 1e-3)}
+
+
+def row_batched(ppa, hip):
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    frames = workloads.trajectory()
+    F = len(frames)
+    sizes = [f.points.shape[0] for f in frames]
+    boxes = [ppa.Box(f.L, f.tilt, f.dim) for f in frames]
+    bins, r_max = 128, 2.5
+    pts = torch.as_tensor(np.concatenate([f.points for f in frames])).cuda()
+    plan = ppa.BatchPlan(boxes, sizes, bins, r_max)
+    hist0, nl0 = plan.run(pts)  # sizes the per-frame outputs below
+    total_pairs = nl0.n_pairs
+    tune_ms, cfg = plan.autotune(pts, reps=2)
+    hist = torch.zeros((F, bins), dtype=torch.int64, device="cuda")
+    launch = plan.graph(pts, hist)
+    batched_ms = timed(launch, 5, warmup=1)
+    torch.cuda.synchronize()
+    if plan.ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+
+    # per-frame baseline: one eager ppa_rdf call (own cell list, list + RDF)
+    # per frame on the same stream, outputs in per-frame slices
+    off = nl0.offsets.cpu().numpy()
+    pb = plan.offsets_host
+    ws = ppa.Workspace()
+    need = max(ppa.workspace_bytes(b, m, 0, r_max, ppa.PPA_WS_NLIST) for b, m in zip(boxes, sizes))
+    wptr, wlen = ws.get(need)
+    pf_hist = torch.zeros((F, bins), dtype=torch.int64, device="cuda")
+    pf_off = torch.empty(int(pb[-1]) + F, dtype=torch.int64, device="cuda")
+    pf_cnt = torch.empty(int(pb[-1]), dtype=torch.int32, device="cuda")
+    cap = [int(off[pb[f + 1]] - off[pb[f]]) + 1024 for f in range(F)]
+    cbase = np.concatenate([[0], np.cumsum(cap)])
+    pf_idx = torch.empty(int(cbase[-1]), dtype=torch.int32, device="cuda")
+    pf_dist = torch.empty(int(cbase[-1]), dtype=torch.float32, device="cuda")
+    pf_np = torch.zeros(F, dtype=torch.int64, device="cuda")
+    cboxes = [b.c() for b in boxes]
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    base = pts.data_ptr()
+    es = pf_idx.element_size()
+
+    def per_frame():
+        for f in range(F):
+            m = sizes[f]
+            rc = L.ppa_rdf(ctypes.byref(cboxes[f]), ctypes.c_void_p(base + 12 * int(pb[f])), m, None,
+                           m, bins, 0.0, r_max, 1, 0, wptr, wlen,
+                           ctypes.c_void_p(pf_hist.data_ptr() + 8 * bins * f),
+                           ctypes.c_void_p(pf_off.data_ptr() + 8 * (int(pb[f]) + f)),
+                           ctypes.c_void_p(pf_cnt.data_ptr() + 4 * int(pb[f])),
+                           ctypes.c_void_p(pf_idx.data_ptr() + es * int(cbase[f])),
+                           ctypes.c_void_p(pf_dist.data_ptr() + 4 * int(cbase[f])), cap[f],
+                           ctypes.c_void_p(pf_np.data_ptr() + 8 * f), sptr)
+            if rc != 0:
+                raise RuntimeError(L.ppa_last_error().decode())
+    per_frame_ms = timed(per_frame, 3, warmup=1)
+    if ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+    assert int(pf_np.sum().item()) == total_pairs
+    return {"workload": "256 frames, N_f log-uniform in [1e3, 2e5] (total %d), own triclinic boxes, "
+                        "ball r_max=2.5 -> NeighborList + per-frame RDF 128 bins" % int(pb[-1]),
+            "frames": F, "points": int(pb[-1]), "pairs": total_pairs,
+            "batched_ms": batched_ms, "batched_frames_per_s": F / (batched_ms * 1e-3),
+            "batched_pairs_per_s": total_pairs / (batched_ms * 1e-3),
+            "per_frame_ms": per_frame_ms, "per_frame_frames_per_s": F / (per_frame_ms * 1e-3),
+            "speedup": per_frame_ms / batched_ms,
+            "autotuned": cfg, "autotune_ms": tune_ms,
+            "note": "batched = one HIP-graph launch of the autotuned plan; per-frame = 256 eager "
+                    "ppa_rdf calls with list, each building its own cell list"}
+
+
+def row_smooth(ppa, hip):
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s, _ = workloads.smooth_target_pair()
+    n = s.points.shape[0]
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    bins, r_max, sigma = 200, 3.0, 0.02
+    ws = ppa.Workspace()
+    wptr, wlen = ws.get(ppa.smooth_rdf_workspace_bytes(box, n, bins, r_max, sigma))
+    h = torch.zeros(bins, dtype=torch.float64, device="cuda")
+    gh = torch.as_tensor(np.random.default_rng(0).normal(size=bins)).cuda()
+    grad = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    cb = box.c()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def fwd():
+        rc = L.ppa_smooth_rdf_fwd(ctypes.byref(cb), p(pts), n, bins, r_max, sigma, 0, wptr, wlen,
+                                  p(h), sptr)
+        if rc != 0:
+            raise RuntimeError(L.ppa_last_error().decode())
+
+    def bwd():
+        rc = L.ppa_smooth_rdf_bwd(ctypes.byref(cb), p(pts), n, bins, r_max, sigma, p(gh), 0, wptr,
+                                  wlen, p(grad), sptr)
+        if rc != 0:
+            raise RuntimeError(L.ppa_last_error().decode())
+    fwd_ms = timed(fwd, 5, warmup=2)
+    bwd_ms = timed(bwd, 5, warmup=2)
+    if ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+    nl = ppa.query_ball(box, pts, r_max + 8 * sigma, with_dist=False)
+    return {"workload": "perturbed simple-cubic N=131,072, density 0.9, sigma 0.02, 200 bins on "
+                        "[0,3), pairs within 3.16",
+            "pairs": nl.n_pairs, "forward_ms": fwd_ms, "adjoint_ms": bwd_ms,
+            "forward_pairs_per_s": nl.n_pairs / (fwd_ms * 1e-3),
+            "adjoint_pairs_per_s": nl.n_pairs / (bwd_ms * 1e-3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1906_06317_amd as ppa
+    torch.cuda.set_device(0)
+    hip = Hip()
+    ppa.lib()
+    line, rows, sysm = headline(args, ppa, hip)
+    if not args.no_rows:
+        rows["pmft2d"] = row_pmft(ppa, hip)
+        rows["batched"] = row_batched(ppa, hip)
+        rows["smooth_rdf"] = row_smooth(ppa, hip)
+    line["rows"] = rows
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, P, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+        line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
