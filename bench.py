@@ -44,6 +44,9 @@ def parse():
                     help="target CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (a known-size reference for "
+                         "memory-traffic counters)")
     return ap.parse_args()
 
 
@@ -411,6 +414,12 @@ def main():
     torch.cuda.set_device(0)
     hip = Hip()
     ppa.lib()
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     line, rows, sysm = headline(args, ppa, hip)
     if not args.no_rows:
         rows["pmft2d"] = row_pmft(ppa, hip)

@@ -249,9 +249,9 @@ __global__ void __launch_bounds__(kBlock) knn_kernel(const KnnArgs a)
                                          G.off[threadIdx.x][2], 0.f);
     __syncthreads();
     const PairIn in{a.cand, a.cand_start, a.qsorted, a.q_start};
-    int t0, t1;
-    wave_tiles(G.ncells, wv, t0, t1);
-    for (int tile = t0; tile < t1; ++tile) {
+    int t0, t1, stride;
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
+    for (int tile = t0; tile < t1; tile += stride) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;

@@ -86,6 +86,26 @@ __device__ __forceinline__ void wave_tiles(int ncells, int wv, int& t0, int& t1)
     wave_tiles_n<kWavesPerBlock>(ncells, wv, t0, t1);
 }
 
+// Home cells of this wavefront, interleaved: the cells of XCD x (workgroups
+// dispatched round-robin over the 8 XCDs) are [x C / 8, (x + 1) C / 8), and
+// its wavefronts take them in turn, t0, t0 + stride, ... below t1, so the
+// cells in flight on an XCD at any time are neighbours and share their
+// stencil cells in that XCD's L2.
+template <int WPB>
+__device__ __forceinline__ void wave_tiles_interleaved(int ncells, int wv, int& t0, int& t1,
+                                                       int& stride)
+{
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7;
+    const int per = G >> 3;  // workgroups per XCD
+    const int c0 = (int)((long long)xcd * ncells / 8);
+    const int c1 = (int)((long long)(xcd + 1) * ncells / 8);
+    t0 = uniform(c0 + (blockIdx.x >> 3) * WPB + wv);
+    t1 = uniform(c1);
+    stride = per * WPB;
+    if ((int)(blockIdx.x >> 3) >= per) t1 = t0;  // launches are whole multiples of 8
+}
+
 // Stencil slot -> offset code d = (dx+1) + 3 (dy+1) + 9 (dz+1): the home
 // cell (centre code) is slot 0 and takes the place of code 0.
 __device__ __forceinline__ int stencil_code(int s, int nsten)

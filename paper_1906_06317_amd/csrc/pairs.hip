@@ -123,9 +123,9 @@ __global__ void __launch_bounds__(kBlock, 5) count_kernel(const PairIn in, const
                                          G.off[threadIdx.x][2], 0.f);
     __syncthreads();
     const GeomView V = view_of(G);
-    int t0, t1;
-    wave_tiles(G.ncells, wv, t0, t1);
-    for (int tile = t0; tile < t1; ++tile) {
+    int t0, t1, stride;
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
+    for (int tile = t0; tile < t1; tile += stride) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
@@ -213,8 +213,10 @@ struct Filler {
     __device__ __forceinline__ void emit(long long dst, int id, float r)
     {
         if (dst < O.capacity) {
-            O.point_idx[dst] = id - id_base;
-            if (O.dist) O.dist[dst] = r;
+            // the list is written once and read by a later kernel: stream it
+            // past the caches, which keep the stencil cells
+            __builtin_nontemporal_store(id - id_base, &O.point_idx[dst]);
+            if (O.dist) __builtin_nontemporal_store(r, &O.dist[dst]);
         } else {
             over = true;
         }
@@ -432,9 +434,9 @@ __global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const 
     }
     Filler<DIM, EXCL, NL, HIST> F(s_w[wv], O, lds_hist ? s_hist : nullptr, lane);
     const GeomView V = view_of(G);
-    int t0, t1;
-    wave_tiles(G.ncells, wv, t0, t1);
-    for (int tile = t0; tile < t1; ++tile) {
+    int t0, t1, stride;
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
+    for (int tile = t0; tile < t1; tile += stride) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;

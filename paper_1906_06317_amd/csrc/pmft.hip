@@ -105,9 +105,9 @@ __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
     __syncthreads();
     const PairIn in{a.cand, a.cand_start, a.qsorted, a.q_start};
     StencilLds& S = L.st[wv];
-    int t0, t1;
-    wave_tiles_n<kPmftWaves>(G.ncells, wv, t0, t1);
-    for (int tile = t0; tile < t1; ++tile) {
+    int t0, t1, stride;
+    wave_tiles_interleaved<kPmftWaves>(G.ncells, wv, t0, t1, stride);
+    for (int tile = t0; tile < t1; tile += stride) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;

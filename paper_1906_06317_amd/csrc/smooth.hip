@@ -211,10 +211,10 @@ __global__ void __launch_bounds__(kBlock) smooth_kernel(const SmoothArgs a)
     __syncthreads();
     const PairIn in{a.cand, a.cand_start, a.cand, a.cand_start};
     const float r2s = G.r2max;
-    int t0, t1;
-    wave_tiles(G.ncells, wv, t0, t1);
+    int t0, t1, stride;
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
     int nh = 0;
-    for (int tile = t0; tile < t1; ++tile) {
+    for (int tile = t0; tile < t1; tile += stride) {
         const int q0 = in.q_start[tile];
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
