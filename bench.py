@@ -33,6 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fill_kernel_fcc1M_traffic.md")
+# sources the fill kernel is compiled from: a recorded traffic figure is
+# reported only while they are unchanged
+FILL_SOURCES = ["paper_1906_06317_amd/csrc/pairs.hip", "paper_1906_06317_amd/csrc/pair_common.hpp",
+                "paper_1906_06317_amd/csrc/internal.hpp"]
 
 
 def parse():
@@ -40,10 +45,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="target CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the fill kernel's source hash (for the traffic record) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for "
                          "memory-traffic counters)")
@@ -76,6 +83,31 @@ class Hip:
     def destroy(self, evs):
         for e in evs:
             self.L.hipEventDestroy(e)
+
+
+def fill_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FILL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per fill-kernel launch from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    when the record is missing or the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_RECORD):
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
+            k, v = line.strip().strip("`").split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != fill_source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def timed(fn, reps, warmup=1):
@@ -230,7 +262,7 @@ def headline(args, ppa, hip):
                    "n_points": n, "r_max": r_max, "bins": bins, "k": k, "n_pairs": P,
                    "rows": "CSR in query order (count, scan, fill)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "kernel": "fill_kernel (ball list + RDF)", "kernel_ms": fill_ms,
                      "algorithmic_bytes": alg_bytes, "count_kernel_ms": count_ms},
     }
@@ -404,6 +436,9 @@ def row_smooth(ppa, hip):
 
 def main():
     args = parse()
+    if args.source_hash:
+        print(fill_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
