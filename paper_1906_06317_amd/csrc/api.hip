@@ -523,12 +523,14 @@ int pmft_plan(const BoxPrep& bp, int64_t n, int32_t nbx, int32_t nby, float x_ma
 }
 
 size_t pmft_layout(const PmftPlan& P, int64_t n, int64_t nq_sep, void* base_v, Workspace* W,
-                   unsigned** partial)
+                   unsigned** partial, unsigned** level2)
 {
     char* base = (char*)base_v;
     size_t off = workspace_layout(P.g, n, nq_sep, 0, base_v, W);
     *partial = base ? (unsigned*)(base + off) : nullptr;
-    off += sizeof(unsigned) * (size_t)P.blocks * (size_t)P.words;
+    off = (off + sizeof(unsigned) * (size_t)P.blocks * (size_t)P.words + 255) & ~(size_t)255;
+    *level2 = base ? (unsigned*)(base + off) : nullptr;
+    off += sizeof(unsigned) * (size_t)partial_rows(P.blocks) * (size_t)P.words;
     return (off + 255) & ~(size_t)255;
 }
 
@@ -553,11 +555,12 @@ int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
     const int64_t nq_sep = qpts ? nq : 0;
     Workspace W{};
     unsigned* partial = nullptr;
-    const size_t need = pmft_layout(P, n, nq_sep, nullptr, &W, &partial);
+    unsigned* level2 = nullptr;
+    const size_t need = pmft_layout(P, n, nq_sep, nullptr, &W, &partial, &level2);
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
         return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                          need, ws_bytes);
-    pmft_layout(P, n, nq_sep, ws, &W, &partial);
+    pmft_layout(P, n, nq_sep, ws, &W, &partial, &level2);
     if (nq == 0) return PPA_OK;
     const Grid& g = P.g;
     launch_zero(W, g, qpts != nullptr, nullptr, 0, s);
@@ -584,6 +587,7 @@ int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
     A.inv_dy = (float)((double)nby / (2.0 * y_max));
     A.words = P.words;
     A.partial = partial;
+    A.level2 = level2;
     A.counts = counts;
     A.table = P.table;
     ProfileEvents pe = take_profile_events();
@@ -618,12 +622,14 @@ int smooth_plan(const BoxPrep& bp, int64_t n, int32_t bins, float r_max, float s
 }
 
 size_t smooth_layout(const SmoothPlan& P, int64_t n, int32_t bins, void* base_v, Workspace* W,
-                     double** partial)
+                     double** partial, double** level2)
 {
     char* base = (char*)base_v;
     size_t off = workspace_layout(P.g, n, 0, 0, base_v, W);
     *partial = base ? (double*)(base + off) : nullptr;
-    off += sizeof(double) * (size_t)P.blocks * (size_t)bins;
+    off = (off + sizeof(double) * (size_t)P.blocks * (size_t)bins + 255) & ~(size_t)255;
+    *level2 = base ? (double*)(base + off) : nullptr;
+    off += sizeof(double) * (size_t)partial_rows(P.blocks) * (size_t)bins;
     return (off + 255) & ~(size_t)255;
 }
 
@@ -643,11 +649,12 @@ int run_smooth(const ppa_box* box, const float* pts, int64_t n, int32_t bins, fl
     if ((rc = smooth_plan(bp, n, bins, r_max, sigma, adjoint, &P))) return rc;
     Workspace W{};
     double* partial = nullptr;
-    const size_t need = smooth_layout(P, n, bins, nullptr, &W, &partial);
+    double* level2 = nullptr;
+    const size_t need = smooth_layout(P, n, bins, nullptr, &W, &partial, &level2);
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
         return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                          need, ws_bytes);
-    smooth_layout(P, n, bins, ws, &W, &partial);
+    smooth_layout(P, n, bins, ws, &W, &partial, &level2);
     if (n == 0) return PPA_OK;
     const Grid& g = P.g;
     launch_zero(W, g, false, nullptr, 0, s);
@@ -676,11 +683,13 @@ int run_smooth(const ppa_box* box, const float* pts, int64_t n, int32_t bins, fl
     A.bins = bins;
     A.dr = (double)r_max / bins;
     A.w8 = 8.0 * (double)sigma;
+    A.inv_dr = (float)((double)bins / (double)r_max);
     const double sg = sigma;
     A.k2 = (float)(1.4426950408889634 / (2.0 * sg * sg));
     A.hscale = (float)(A.dr / (sg * sqrt(2.0 * M_PI)));
     A.gscale = (float)(A.dr / (sg * sg * sg * sqrt(2.0 * M_PI)));
     A.partial = partial;
+    A.level2 = level2;
     A.h = h;
     A.grad_h = grad_h;
     A.grad = grad;
@@ -822,7 +831,8 @@ int ppa_pmft2d_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_
     if ((rc = pmft_plan(bp, n, nbx, nby, x_max, y_max, r_max, &P))) return rc;
     Workspace W{};
     unsigned* partial = nullptr;
-    *bytes = pmft_layout(P, n, nq, nullptr, &W, &partial);
+    unsigned* level2 = nullptr;
+    *bytes = pmft_layout(P, n, nq, nullptr, &W, &partial, &level2);
     return PPA_OK;
 }
 
@@ -848,8 +858,9 @@ int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, 
     if ((rc = smooth_plan(bp, n, bins, r_max, sigma, true, &Pb))) return rc;
     Workspace W{};
     double* partial = nullptr;
-    const size_t a = smooth_layout(P, n, bins, nullptr, &W, &partial);
-    const size_t b = smooth_layout(Pb, n, bins, nullptr, &W, &partial);
+    double* level2 = nullptr;
+    const size_t a = smooth_layout(P, n, bins, nullptr, &W, &partial, &level2);
+    const size_t b = smooth_layout(Pb, n, bins, nullptr, &W, &partial, &level2);
     *bytes = a > b ? a : b;
     return PPA_OK;
 }

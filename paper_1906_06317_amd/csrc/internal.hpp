@@ -83,6 +83,11 @@ struct FrameInfo {
     float off[27][4];      // stencil offsets M (delta / n), float32
 };
 
+// Per-workgroup partial arrays are summed in two stages; the first sums
+// kPartialRowsPer of them at a time into one row of first-stage sums.
+constexpr int kPartialRowsPer = 32;
+inline int partial_rows(int G) { return (G + kPartialRowsPer - 1) / kPartialRowsPer; }
+
 // Host helpers (api.hip).
 int prepare_box(const ppa_box* box, BoxPrep* out);
 int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g);
@@ -215,6 +220,7 @@ struct PmftArgs {
     float inv_dx, inv_dy;     // bins per unit length
     int words;                // LDS words of the compacted histogram (0: global atomics)
     unsigned* partial;        // [gridDim.x][words] per-workgroup histograms
+    unsigned* level2;         // [ceil(gridDim.x / 32)][words] first-stage sums
     unsigned* counts;         // [nbx * nby] accumulated
     PmftTable table;
 };
@@ -236,10 +242,12 @@ struct SmoothArgs {
     int bins;
     double dr;                // r_max / bins
     double w8;                // window half-width 8 sigma
+    float inv_dr;             // bins / r_max
     float k2;                 // log2(e) / (2 sigma^2)
     float hscale;             // dr / (sigma sqrt(2 pi)): forward weight of exp(-u^2/2s^2)
     float gscale;             // dr / (sigma^3 sqrt(2 pi)): adjoint weight of u exp(-u^2/2s^2)
     double* partial;          // forward: [gridDim.x][bins]
+    double* level2;           // forward: [ceil(gridDim.x / 32)][bins] first-stage sums
     double* h;                // forward: [bins], accumulated
     const double* grad_h;     // adjoint: dL/dh [bins]
     float* grad;              // adjoint: dL/dp [n][3], written

@@ -302,6 +302,28 @@ struct QueryChunk {
 };
 
 
+// Sum of per-workgroup partial arrays, first stage: partial[g][w] for
+// g < G, w < W; workgroup (x, y) sums rows [y per, (y + 1) per) for 64
+// consecutive w into level2[y][w].  Fixed order, so the result does not
+// depend on timing.  Launch: grid (ceil(W / 64), ceil(G / per)), 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256) partial_sum_stage1(const T* __restrict__ partial, int G,
+                                                          int W, int per, T* __restrict__ level2)
+{
+    __shared__ T s[4][64];
+    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int w = blockIdx.x * 64 + lane;
+    const int g0 = blockIdx.y * per;
+    const int g1 = min(G, g0 + per);
+    T acc = 0;
+    if (w < W)
+        for (int g = g0 + sub; g < g1; g += 4) acc += partial[(size_t)g * W + w];
+    s[sub][lane] = acc;
+    __syncthreads();
+    if (sub == 0 && w < W)
+        level2[(size_t)blockIdx.y * W + w] = (s[0][lane] + s[1][lane]) + (s[2][lane] + s[3][lane]);
+}
+
 // Workgroups for a persistent launch of `kernel`: as many as fit on the
 // device at once, at least one home cell per wavefront, a multiple of 8.
 template <typename K>

@@ -476,6 +476,27 @@ __global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const 
 // frame-local point indices, the frame's histogram) when its cells cross
 // into the next frame, which happens at most a few times per wavefront.
 // ---------------------------------------------------------------------------
+// Home cells of a wavefront in a batch: the cells of XCD x (workgroups
+// dispatched round-robin over the 8 XCDs) are [c0, c1) = [x C / 8,
+// (x + 1) C / 8), cut into runs of kBatchRun consecutive cells dealt to the
+// XCD's wavefronts in turn (runs k0, k0 + kstride, ...): neighbouring runs
+// are in flight together and share stencil cells in the XCD's L2, while a
+// run rarely crosses into another frame.  Returns false for workgroups
+// beyond whole multiples of 8.
+constexpr int kBatchRun = 16;
+
+__device__ __forceinline__ bool batch_chunks(int ncells, int wv, int& c0, int& c1, int& k0,
+                                             int& kstride)
+{
+    const int per = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    c0 = uniform((int)((long long)xcd * ncells / 8));
+    c1 = uniform((int)((long long)(xcd + 1) * ncells / 8));
+    k0 = uniform((int)(blockIdx.x >> 3) * kWavesPerBlock + wv);
+    kstride = per * kWavesPerBlock;
+    return (int)(blockIdx.x >> 3) < per;
+}
+
 // Frame of global cell `tile`: the last f with cell_base[f] <= tile.
 __device__ __forceinline__ int frame_of(const BatchGeom& B, int tile)
 {
@@ -518,16 +539,14 @@ __global__ void __launch_bounds__(kBlock, 5) count_batch_kernel(const PairIn in,
     const int wv = uniform(threadIdx.x / kWave);
     StencilLds& S = s_st[wv];
     float4* off = s_off[wv];
-    int t0, t1;
-    wave_tiles(B.ncells, wv, t0, t1);
-    if (t0 >= t1) return;
-    int f = frame_of(B, t0);
-    GeomView V = load_frame(B, f, off, lane);
-    int next = B.cell_base[f + 1];
-    for (int tile = t0; tile < t1; ++tile) {
+    int c0, c1, k0, kstride;
+    if (!batch_chunks(B.ncells, wv, c0, c1, k0, kstride)) return;
+    int f = -1, next = -1;
+    GeomView V;
+    for (int k = k0; c0 + k * kBatchRun < c1; k += kstride)
+    for (int tile = c0 + k * kBatchRun, te = min(tile + kBatchRun, c1); tile < te; ++tile) {
         if (tile >= next) {
-            while (B.cell_base[f + 1] <= tile) ++f;
-            f = uniform(f);
+            f = frame_of(B, tile);
             V = load_frame(B, f, off, lane);
             next = B.cell_base[f + 1];
         }
@@ -580,22 +599,18 @@ __global__ void __launch_bounds__(kBlock, 4) fill_batch_kernel(const PairIn in, 
         for (int b = lane; b < O.bins; b += kWave) h[b] = 0u;
     if (lane < kHitCap / 64) s_w[wv].starts[lane] = 0ull;
     wave_sync();
-    int t0, t1;
-    wave_tiles(B.ncells, wv, t0, t1);
-    if (t0 >= t1) return;
+    int c0, c1, k0, kstride;
+    if (!batch_chunks(B.ncells, wv, c0, c1, k0, kstride)) return;
     Filler<DIM, EXCL, true, true> F(s_w[wv], O, h, lane);
-    int f = frame_of(B, t0);
-    GeomView V = load_frame(B, f, off, lane);
-    F.ghist = O.hist + (size_t)f * O.bins;
-    F.id_base = uniform(B.frames[f].point_base);
-    int next = B.cell_base[f + 1];
-    for (int tile = t0; tile < t1; ++tile) {
+    int f = -1, next = -1;
+    GeomView V;
+    for (int k = k0; c0 + k * kBatchRun < c1; k += kstride)
+    for (int tile = c0 + k * kBatchRun, te = min(tile + kBatchRun, c1); tile < te; ++tile) {
         if (tile >= next) {
             // buffered hits belong to the old frame: write them and its bins first
             if (F.nh > 0) F.flush();
-            if (lds_hist) merge_wave_hist(h, F.ghist, O.bins, lane);
-            while (B.cell_base[f + 1] <= tile) ++f;
-            f = uniform(f);
+            if (lds_hist && f >= 0) merge_wave_hist(h, F.ghist, O.bins, lane);
+            f = frame_of(B, tile);
             V = load_frame(B, f, off, lane);
             F.ghist = O.hist + (size_t)f * O.bins;
             F.id_base = uniform(B.frames[f].point_base);
@@ -616,7 +631,7 @@ __global__ void __launch_bounds__(kBlock, 4) fill_batch_kernel(const PairIn in, 
         }
     }
     if (F.nh > 0) F.flush();
-    if (lds_hist) merge_wave_hist(h, F.ghist, O.bins, lane);
+    if (lds_hist && f >= 0) merge_wave_hist(h, F.ghist, O.bins, lane);
     if (__ballot(F.over) && lane == 0) atomicOr(O.status, kStatusCapacity);
 }
 

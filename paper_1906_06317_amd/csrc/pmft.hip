@@ -130,9 +130,10 @@ __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
     }
 }
 
-// counts[ix][iy] += sum over workgroups of their partial histograms.
-__global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __restrict__ partial,
-                                                          int blocks, int words, int nbx, int nby,
+// counts[ix][iy] += the first stage's sums (level2[gs][word]) of the
+// workgroups' partial histograms.
+__global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __restrict__ level2,
+                                                          int rows, int words, int nbx, int nby,
                                                           PmftTable table,
                                                           unsigned* __restrict__ counts)
 {
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __rest
     if (w < 0 || w >= table.base[ix + 1] - table.base[ix]) return;
     const int idx = table.base[ix] + w;
     unsigned sum = 0;
-    for (int g = 0; g < blocks; ++g) sum += partial[(size_t)g * words + idx];
+    for (int g = 0; g < rows; ++g) sum += level2[(size_t)g * words + idx];
     counts[b] += sum;
 }
 
@@ -194,9 +195,12 @@ void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s)
         (void)hipFuncSetAttribute((const void*)pmft_kernel<true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(pmft_kernel<true>, dim3(blocks), dim3(kPmftBlock), lds, s, a);
+        const int rows = partial_rows(blocks);
+        hipLaunchKernelGGL(partial_sum_stage1<unsigned>, dim3((a.words + 63) / 64, rows),
+                           dim3(256), 0, s, a.partial, blocks, a.words, kPartialRowsPer, a.level2);
         const int nb = a.nbx * a.nby;
-        hipLaunchKernelGGL(pmft_reduce_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.partial,
-                           blocks, a.words, a.nbx, a.nby, a.table, a.counts);
+        hipLaunchKernelGGL(pmft_reduce_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.level2,
+                           rows, a.words, a.nbx, a.nby, a.table, a.counts);
     } else {
         hipLaunchKernelGGL(pmft_kernel<false>, dim3(blocks), dim3(kPmftBlock), 0, s, a);
     }

@@ -97,12 +97,16 @@ __device__ __forceinline__ void hit_vector(const SmoothArgs& a, const SmoothShar
     dz = DIM == 3 ? ((double)v.z - (double)q.z) + L.offd[j][2] : 0.0;
 }
 
-// Bins of the window around r: |c_b - r| <= 8 s, inside [0, bins).
+// Bins of the window around r: |c_b - r| <= 8 s, inside [0, bins).  The
+// bounds are found in float32 (a bin at the edge carries weight e^-32, so
+// where rounding puts the edge does not matter); the offset of the first
+// bin centre from r is exact to float64 before rounding.
 __device__ __forceinline__ void window(const SmoothArgs& a, double r, int& b0, int& b1, float& u0)
 {
-    b0 = max(0, (int)ceil((r - a.w8) / a.dr - 0.5));
-    b1 = min(a.bins - 1, (int)floor((r + a.w8) / a.dr - 0.5));
-    u0 = (float)(((double)b0 + 0.5) * a.dr - r);
+    const float rf = (float)r, w8 = (float)a.w8;
+    b0 = max(0, (int)ceilf(fmaf(rf - w8, a.inv_dr, -0.5f)));
+    b1 = min(a.bins - 1, (int)floorf(fmaf(rf + w8, a.inv_dr, -0.5f)));
+    u0 = (float)fma((double)b0 + 0.5, a.dr, -r);
 }
 
 // Hits of query t (scalar) against NS slots, appended to the buffer.
@@ -267,14 +271,15 @@ __global__ void __launch_bounds__(kBlock) smooth_kernel(const SmoothArgs a)
     }
 }
 
-__global__ void __launch_bounds__(256) smooth_reduce_kernel(const double* __restrict__ partial,
-                                                            int blocks, int bins,
+// h[b] += the first stage's sums (level2[row][b]) of the partial histograms.
+__global__ void __launch_bounds__(256) smooth_reduce_kernel(const double* __restrict__ level2,
+                                                            int rows, int bins,
                                                             double* __restrict__ h)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= bins) return;
     double sum = 0.0;
-    for (int g = 0; g < blocks; ++g) sum += partial[(size_t)g * bins + b];
+    for (int g = 0; g < rows; ++g) sum += level2[(size_t)g * bins + b];
     h[b] += sum;
 }
 
@@ -316,8 +321,11 @@ void launch_smooth_fwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s)
         hipLaunchKernelGGL((smooth_kernel<3, false>), dim3(blocks), dim3(kBlock), dyn, s, a);
     else
         hipLaunchKernelGGL((smooth_kernel<2, false>), dim3(blocks), dim3(kBlock), dyn, s, a);
+    const int rows = partial_rows(blocks);
+    hipLaunchKernelGGL(partial_sum_stage1<double>, dim3((a.bins + 63) / 64, rows), dim3(256), 0, s,
+                       a.partial, blocks, a.bins, kPartialRowsPer, a.level2);
     hipLaunchKernelGGL(smooth_reduce_kernel, dim3((a.bins + 255) / 256), dim3(256), 0, s,
-                       a.partial, blocks, a.bins, a.h);
+                       a.level2, rows, a.bins, a.h);
 }
 
 void launch_smooth_bwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s)
