@@ -280,6 +280,21 @@ def headline(args, ppa, hip):
     return line, rows, sysm
 
 
+def lds_atomic_peak(ppa):
+    """LDS atomic adds per second of the device (microbenchmark, random bins)."""
+    import torch
+    L = ppa.lib()
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for lb in (8, 14):
+        blocks, iters = 2048, 256
+        ms = timed(lambda: L.ppa_probe_lds_atomics(lb, iters, blocks, ctypes.c_void_p(out.data_ptr()),
+                                                   sptr), 5)
+        res[f"{1 << lb}_bins_per_s"] = blocks * 256 * 8 * iters / (ms * 1e-3)
+    return res
+
+
 def row_pmft(ppa, hip):
     import numpy as np
     import torch
@@ -456,8 +471,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     line, rows, sysm = headline(args, ppa, hip)
+    peak = lds_atomic_peak(ppa)
+    rows["lds_atomic_probe"] = peak
+    rows["ball_rdf"]["fill_lds_atomics_per_s"] = line["config"]["n_pairs"] / (
+        line["roofline"]["kernel_ms"] * 1e-3)
+    rows["ball_rdf"]["fill_frac_of_lds_atomic_probe"] = (
+        rows["ball_rdf"]["fill_lds_atomics_per_s"] / peak["256_bins_per_s"])
     if not args.no_rows:
         rows["pmft2d"] = row_pmft(ppa, hip)
+        rows["pmft2d"]["binning_lds_atomics_per_s"] = rows["pmft2d"]["pairs"] / (
+            rows["pmft2d"]["binning_kernels_ms"] * 1e-3)
+        rows["pmft2d"]["frac_of_lds_atomic_probe"] = (
+            rows["pmft2d"]["binning_lds_atomics_per_s"] / peak["16384_bins_per_s"])
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
     line["rows"] = rows

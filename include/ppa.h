@@ -310,6 +310,15 @@ int ppa_batch_graph_destroy(ppa_batch_graph* graph);
 int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t fill_start,
                      hipEvent_t fill_stop);
 
+/* Measurement hook: launches `blocks` workgroups of 256 threads that each
+ * add 1 to pseudo-random bins of an LDS histogram of 2^log2_bins 32-bit
+ * counters, 8 x iters atomics per thread (log2_bins in [1, 14]), then add
+ * their totals to *out_dev (uint32 device, accumulated).  Timed by the
+ * caller, it gives the device's LDS atomic rate, the reference for the
+ * histogram kernels' binning rates. */
+int ppa_probe_lds_atomics(int32_t log2_bins, int32_t iters, int32_t blocks, uint32_t* out_dev,
+                          hipStream_t stream);
+
 /* Waits for the stream and returns the device status of the last call that
  * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE or, for a
  * k-nearest query, PPA_ERANGE). */

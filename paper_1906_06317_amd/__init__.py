@@ -128,6 +128,7 @@ def lib():
             "ppa_smooth_rdf_bwd": [BP, P, i64, i32, f32, f32, P, i32, P, sz, P, P],
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
+            "ppa_probe_lds_atomics": [i32, i32, i32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)

@@ -38,7 +38,7 @@ using namespace pair;
 
 constexpr int kKnnSlots = 4;    // register slots of the common path (256 candidates)
 constexpr int kKnnIter = 16;    // threshold refinements before a query is deferred
-constexpr float kKnnGrow = 1.3f;  // next guess: this times the previous k-th r^2
+constexpr float kKnnGrow = 1.1f;  // next guess: this times the previous k-th r^2
 constexpr unsigned long long kNoKey = ~0ull;
 
 __device__ __forceinline__ unsigned long long knn_key(float d2, int id)

@@ -110,7 +110,7 @@ __device__ __forceinline__ void count_chunked(const PairIn& in, const GeomView& 
 }
 
 template <int DIM, int EXCL>
-__global__ void __launch_bounds__(kBlock, 5) count_kernel(const PairIn in, const PairGeom G,
+__global__ void __launch_bounds__(kBlock, 6) count_kernel(const PairIn in, const PairGeom G,
                                                        int32_t* __restrict__ counts)
 {
     __shared__ float4 s_off[27];
