@@ -617,7 +617,7 @@ int smooth_plan(const BoxPrep& bp, int64_t n, int32_t bins, float r_max, float s
     int rc;
     if ((rc = check_cutoff(bp, P->r_s))) return rc;
     make_grid(bp, P->r_s, n, &P->g);
-    P->blocks = smooth_workgroups(adjoint, bp.dim);
+    P->blocks = smooth_workgroups(adjoint, bp.dim, bins);
     return PPA_OK;
 }
 
@@ -693,7 +693,14 @@ int run_smooth(const ppa_box* box, const float* pts, int64_t n, int32_t bins, fl
     A.h = h;
     A.grad_h = grad_h;
     A.grad = grad;
-    long long want = ((long long)g.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    // enough work units for four per resident wavefront: split home cells
+    // into parts of their query lists when cells are fewer than that
+    const long long waves = (long long)P.blocks * kWavesPerBlock;
+    long long split = (4 * waves + g.ncells - 1) / g.ncells;
+    const long long per_cell = n / (g.ncells > 0 ? g.ncells : 1);
+    if (split > per_cell / 8) split = per_cell / 8;  // keep >= 8 queries per unit
+    A.split = (int)(split < 1 ? 1 : (split > 16 ? 16 : split));
+    long long want = ((long long)g.ncells * A.split + kWavesPerBlock - 1) / kWavesPerBlock;
     int blocks = (int)(want < P.blocks ? (want + 7) / 8 * 8 : P.blocks);
     if (blocks > P.blocks) blocks = P.blocks;
     ProfileEvents pe = take_profile_events();

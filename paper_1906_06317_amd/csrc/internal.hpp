@@ -246,6 +246,7 @@ struct SmoothArgs {
     float k2;                 // log2(e) / (2 sigma^2)
     float hscale;             // dr / (sigma sqrt(2 pi)): forward weight of exp(-u^2/2s^2)
     float gscale;             // dr / (sigma^3 sqrt(2 pi)): adjoint weight of u exp(-u^2/2s^2)
+    int split;                // work units per home cell (its queries in parts)
     double* partial;          // forward: [gridDim.x][bins]
     double* level2;           // forward: [ceil(gridDim.x / 32)][bins] first-stage sums
     double* h;                // forward: [bins], accumulated
@@ -253,7 +254,7 @@ struct SmoothArgs {
     float* grad;              // adjoint: dL/dp [n][3], written
 };
 
-int smooth_workgroups(bool adjoint, int dim);
+int smooth_workgroups(bool adjoint, int dim, int bins);
 void launch_smooth_fwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s);
 void launch_smooth_bwd(const SmoothArgs& a, int dim, int blocks, hipStream_t s);
 

@@ -139,10 +139,16 @@ __device__ __forceinline__ void flush_fwd(const SmoothArgs& a, const SmoothShare
         int b0, b1;
         float u0;
         window(a, r, b0, b1, u0);
-        for (int b = b0; b <= b1; ++b) {
-            const float u = fmaf((float)(b - b0), drf, u0);
+        // each lane starts its walk at a different bin of its window, so the
+        // lanes of one instruction rarely add to the same bin
+        const int nb = b1 - b0 + 1;
+        int m = nb > 0 ? lane % nb : 0;
+#pragma unroll 4
+        for (int j = 0; j < nb; ++j) {
+            const float u = fmaf((float)m, drf, u0);
             const float v = a.hscale * __builtin_amdgcn_exp2f(-(u * u) * a.k2);
-            atomicAdd(&hist[b], (double)v);
+            atomicAdd(&hist[b0 + m], (double)v);
+            m = m + 1 == nb ? 0 : m + 1;
         }
     }
     wave_sync();
@@ -172,11 +178,16 @@ __device__ __forceinline__ void flush_bwd(const SmoothArgs& a, const SmoothShare
             int b0, b1;
             float u0;
             window(a, r, b0, b1, u0);
-            // the window's terms change sign with u: sum them in float64
+            // the window's terms change sign with u: sum them in float64;
+            // the walk starts at a lane-dependent bin (fewer LDS conflicts)
             double A = 0.0;
-            for (int b = b0; b <= b1; ++b) {
-                const float u = fmaf((float)(b - b0), drf, u0);
-                A += (double)(G[b] * u * __builtin_amdgcn_exp2f(-(u * u) * a.k2));
+            const int nb = b1 - b0 + 1;
+            int m = nb > 0 ? lane % nb : 0;
+#pragma unroll 4
+            for (int j = 0; j < nb; ++j) {
+                const float u = fmaf((float)m, drf, u0);
+                A += (double)(G[b0 + m] * u * __builtin_amdgcn_exp2f(-(u * u) * a.k2));
+                m = m + 1 == nb ? 0 : m + 1;
             }
             const double f = -2.0 * A / r;
             ax = fma(f, dx, ax);
@@ -215,12 +226,16 @@ __global__ void __launch_bounds__(kBlock) smooth_kernel(const SmoothArgs a)
     __syncthreads();
     const PairIn in{a.cand, a.cand_start, a.cand, a.cand_start};
     const float r2s = G.r2max;
+    // work units: each home cell's queries in a.split parts (more units than
+    // cells keep enough wavefronts busy when cells are few and full)
     int t0, t1, stride;
-    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells * a.split, wv, t0, t1, stride);
     int nh = 0;
-    for (int tile = t0; tile < t1; tile += stride) {
-        const int q0 = in.q_start[tile];
-        const int q1 = in.q_start[tile + 1];
+    for (int unit = t0; unit < t1; unit += stride) {
+        const int tile = unit / a.split, part = unit - tile * a.split;
+        const int qa = in.q_start[tile], qb = in.q_start[tile + 1];
+        const int q0 = qa + (int)((long long)(qb - qa) * part / a.split);
+        const int q1 = qa + (int)((long long)(qb - qa) * (part + 1) / a.split);
         if (q0 == q1) continue;
         const int C = stencil<DIM>(in, G, tile, lane, W.st);
         for (int c0 = q0; c0 < q1; c0 += kWave) {
@@ -306,9 +321,9 @@ int occupancy_blocks(size_t dyn)
 
 // Workgroups of a smoothed-RDF launch (the forward's partial histograms are
 // sized by it): every workgroup the device holds at once, a multiple of 8.
-int smooth_workgroups(bool adjoint, int dim)
+int smooth_workgroups(bool adjoint, int dim, int bins)
 {
-    const size_t dyn = sizeof(double) * kSmoothMaxBins;
+    const size_t dyn = (adjoint ? sizeof(float) : sizeof(double)) * (size_t)bins;
     if (dim == 3)
         return adjoint ? occupancy_blocks<3, true>(dyn) : occupancy_blocks<3, false>(dyn);
     return adjoint ? occupancy_blocks<2, true>(dyn) : occupancy_blocks<2, false>(dyn);
