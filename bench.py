@@ -148,8 +148,16 @@ def cpu_baseline(sysm, target_s):
     dt, _ = run(128)
     nq = int(min(n, max(128, 128 * target_s / max(dt, 1e-3))))
     dt, pairs = run(nq)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": model, "kind": "oracle",
             "sample": f"{nq} random query rows of the same N=1,048,576 system (brute force over "
                       f"all points, FP64), ball list + RDF, {dt:.1f} s"}
 
@@ -278,6 +286,58 @@ def headline(args, ppa, hip):
     rows["knn"]["ms_in_step"] = knn_call
     rows["knn"]["pairs_per_s"] = n * k / (knn_call * 1e-3)
     return line, rows, sysm
+
+
+def copy_bandwidth():
+    """Device-to-device copy rate (GB/s, bytes read + written) of a 1 GiB buffer."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), 10, warmup=2)
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def paper_context(ppa):
+    """The paper's two performance statements, re-measured here as context:
+    the 2D PMFT against the RDF on its workload shape (10 frames x 20,000
+    points, density 3.82, r = 1; the paper gives no bin counts: 100 RDF bins,
+    100 x 100 PMFT bins here), which it found about 3x slower on an Intel Xeon
+    E5-2680 v2; and neighbour finding on random 3D points with about 12
+    neighbours within r = 1 (density 2.865) as N grows."""
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    rng = np.random.default_rng(77)
+    frames = []
+    for f in range(10):
+        s = workloads.uniform(20000, 3.82, seed=700 + f, dim=2)
+        frames.append((s, rng.uniform(0, 2 * math.pi, 20000).astype(np.float32)))
+    boxes = [ppa.Box(s.L, s.tilt, s.dim) for s, _ in frames]
+    pts = [torch.as_tensor(s.points).cuda() for s, _ in frames]
+    ths = [torch.as_tensor(t).cuda() for _, t in frames]
+    h = torch.zeros(100, dtype=torch.int64, device="cuda")
+    c = torch.zeros((100, 100), dtype=torch.uint32, device="cuda")
+    rdf_ms = timed(lambda: [ppa.rdf_counts(b, p, 100, 1.0, counts=h, check=False)
+                            for b, p in zip(boxes, pts)], 5)
+    pmft_ms = timed(lambda: [ppa.pmft2d_counts(b, p, t, 100, 100, 1.0, 1.0, 1.0, counts=c,
+                                               check=False)
+                             for b, p, t in zip(boxes, pts, ths)], 5)
+    scaling = {}
+    for n in (1000, 10000, 100000, 1000000):
+        s = workloads.uniform(n, 2.865, seed=800)
+        b = ppa.Box(s.L, s.tilt, s.dim)
+        p = torch.as_tensor(s.points).cuda()
+        nl = ppa.query_ball(b, p, 1.0)
+        ms = timed(lambda: ppa.query_ball(b, p, 1.0, capacity=nl.n_pairs + 1024, check=False), 5)
+        scaling[str(n)] = {"ms": ms, "pairs": nl.n_pairs, "pairs_per_s": nl.n_pairs / (ms * 1e-3)}
+    return {"pmft_over_rdf_2d": pmft_ms / rdf_ms, "rdf_ms": rdf_ms, "pmft_ms": pmft_ms,
+            "paper_pmft_over_rdf": "about 3 (Intel Xeon E5-2680 v2, CPU threads)",
+            "workload": "10 frames x 20,000 2D points, density 3.82, r=1; 100 RDF bins, "
+                        "100x100 PMFT bins",
+            "neighbor_scaling_3d_uniform_density_2.865_r1": scaling,
+            "note": "the paper prints no absolute numbers; these are context, not a target"}
 
 
 def lds_atomic_peak(ppa):
@@ -471,6 +531,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     line, rows, sysm = headline(args, ppa, hip)
+    copy_gbs = copy_bandwidth()
+    line["roofline"]["measured_copy_GBps"] = copy_gbs
+    line["roofline"]["frac_of_measured_copy"] = line["roofline"]["achieved"] / copy_gbs
     peak = lds_atomic_peak(ppa)
     rows["lds_atomic_probe"] = peak
     rows["ball_rdf"]["fill_lds_atomics_per_s"] = line["config"]["n_pairs"] / (
@@ -485,6 +548,7 @@ def main():
             rows["pmft2d"]["binning_lds_atomics_per_s"] / peak["16384_bins_per_s"])
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
+        rows["paper_context"] = paper_context(ppa)
     line["rows"] = rows
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_seconds)
