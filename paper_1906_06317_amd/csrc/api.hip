@@ -114,6 +114,23 @@ int make_grid(const BoxPrep& b, double r_cut, int64_t n_hint, Grid* g)
     return PPA_OK;
 }
 
+// Grid of the ball query and PMFT: cells of width >= r_cut, widened (by at
+// most 2x per axis) while they would hold fewer than kPairTargetPpc points on
+// average.  One wavefront works on one home cell, so very sparse cells leave
+// most lanes idle; wider cells give each wavefront more queries and more
+// candidates per stencil walk.
+constexpr double kPairTargetPpc = 6.0;
+
+static void pair_grid(const BoxPrep& b, double r_cut, int64_t n, Grid* g)
+{
+    make_grid(b, r_cut, n, g);
+    if (n <= 0) return;
+    const double ppc = (double)n / g->ncells;
+    if (ppc >= kPairTargetPpc) return;
+    const double s = fmin(2.0, pow(kPairTargetPpc / ppc, 1.0 / b.dim));
+    make_grid(b, r_cut * s, n, g);
+}
+
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static void carve_cells(char* base, size_t& off, const Grid& g, int64_t n, CellList* cl)
@@ -263,7 +280,7 @@ int run_pairs(const QueryCall& c)
     if (rc) return rc;
     if ((rc = check_cutoff(bp, c.r_max))) return rc;
     Grid g;
-    make_grid(bp, c.r_max, c.n, &g);
+    pair_grid(bp, c.r_max, c.n, &g);
     Workspace W{};
     const int64_t nq_sep = c.qpts ? c.nq : 0;
     const int32_t lay_flags = c.want_nl ? PPA_WS_NLIST : 0;
@@ -494,7 +511,7 @@ int pmft_plan(const BoxPrep& bp, int64_t n, int32_t nbx, int32_t nby, float x_ma
     if (!(isfinite(r_max) && r_max > 0.f)) return set_error(PPA_EINVAL, "r_max must be positive");
     int rc;
     if ((rc = check_cutoff(bp, r_max))) return rc;
-    make_grid(bp, r_max, n, &P->g);
+    pair_grid(bp, r_max, n, &P->g);
     // bins a bond shorter than r_max can reach: per row ix, the iy range
     // covering |y| < sqrt(r_max^2 - min|x|^2), widened by a bin each side
     P->words = 0;
@@ -759,7 +776,7 @@ int ppa_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, float r_cut, 
     if (rc) return rc;
     if ((rc = check_cutoff(bp, r_cut))) return rc;
     Grid g;
-    make_grid(bp, r_cut, n, &g);
+    pair_grid(bp, r_cut, n, &g);
     Workspace W{};
     *bytes = workspace_layout(g, n, nq, flags, nullptr, &W);
     return PPA_OK;

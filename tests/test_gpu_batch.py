@@ -189,3 +189,18 @@ def test_full_trajectory(ppa):
         # differently: at most a handful per frame
         assert np.abs(h[f] - c).sum() <= max(4, int(1e-6 * c.sum()))
     assert abs(nl.n_pairs - total) <= 256 * 4
+
+
+def test_non_finite_and_capacity_are_reported(ppa):
+    frames = _frames(16, 3, 1000, 2000)
+    plan, pts = _plan(ppa, frames)
+    bad = pts.copy()
+    bad[plan.offsets_host[1] + 4, 0] = np.nan
+    with pytest.raises(ppa.PPAError) as e:
+        plan.run(bad)
+    assert e.value.code == ppa.PPA_ENONFINITE
+    small, pts2 = _plan(ppa, frames, capacity=1000)
+    with pytest.raises(ppa.PPAError) as e:
+        small.run(pts2)
+    assert e.value.code == ppa.PPA_ECAPACITY
+    assert int(small.n_pairs.item()) > 1000  # the true count is still reported

@@ -229,3 +229,12 @@ def test_large_fcc_sampled_rows(ppa):
     assert float(d.max()) < 2.5
     p = nl.point_idx.cpu().numpy().reshape(n, 12)
     assert not np.any(p == np.arange(n)[:, None])
+
+
+def test_non_finite_input_is_reported(ppa):
+    s = workloads.small_uniform(n=500)
+    pts = s.points.copy()
+    pts[17, 1] = np.nan
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.query_knn(_box(s), pts, 6)
+    assert e.value.code == ppa.PPA_ENONFINITE

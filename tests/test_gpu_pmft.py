@@ -138,3 +138,12 @@ def test_fluid_2d_full_size(ppa):
                                        200, 3.0, 3.0, 3.0, exclude_ii=False)
     check_hist(g_s.reshape(-1).astype(np.int64), lo.reshape(-1), hi.reshape(-1))
     assert lo.sum() > 30000
+
+
+def test_non_finite_input_is_reported(ppa):
+    s, th = _fluid(500, 0.7, 16)
+    pts = s.points.copy()
+    pts[3, 0] = np.inf
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.pmft2d_counts(_box(s), pts, th, 20, 20, 2.0, 2.0, 2.0)
+    assert e.value.code == ppa.PPA_ENONFINITE

@@ -179,3 +179,15 @@ def test_full_size_perturbed_lattice(ppa):
     rows = np.sort(np.random.default_rng(6).choice(n, 300, replace=False))
     g_ref = oracle.smooth_rdf_grad(_obox(s), s.points, BINS, R_MAX, SIGMA, gh, rows=rows)
     _check_grad(g[rows], g_ref)
+
+
+def test_non_finite_input_is_reported(ppa):
+    s = workloads.uniform(600, 0.9, seed=80)
+    pts = s.points.copy()
+    pts[5, 2] = np.nan
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.smooth_rdf_h(_box(s), pts, BINS, R_MAX, SIGMA)
+    assert e.value.code == ppa.PPA_ENONFINITE
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.smooth_rdf_grad(_box(s), pts, BINS, R_MAX, SIGMA, np.ones(BINS))
+    assert e.value.code == ppa.PPA_ENONFINITE
