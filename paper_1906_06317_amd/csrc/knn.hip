@@ -188,15 +188,24 @@ __device__ __forceinline__ void knn_tile(const KnnArgs& a, const PairIn& in, con
                 nb += __popcll(m);
             }
             wave_sync();
-            const unsigned long long mine = W.key[lane];
+            // Each key is ranked by one lane of every group of gsz >= cnt
+            // lanes; the groups split the buffer between them (four keys per
+            // step, independent LDS reads) and their partial ranks are summed
+            // across groups.  Past cnt the buffer holds keys that sort last.
+            const int gsz = cnt <= 16 ? 16 : (cnt <= 32 ? 32 : kWave);
+            const int ng = kWave / gsz;
+            const int share = ((cnt + ng - 1) / ng + 3) & ~3;
+            const unsigned long long mine = W.key[lane & (gsz - 1)];
+            const unsigned long long* part = &W.key[(lane / gsz) * share];
             int r = 0;
-            // four keys per step: independent LDS reads overlap their latency
-            for (int u = 0; u < cnt; u += 4) {
-                const ulonglong2 a2 = *reinterpret_cast<const ulonglong2*>(&W.key[u]);
-                const ulonglong2 b2 = *reinterpret_cast<const ulonglong2*>(&W.key[u + 2]);
+            for (int u = 0; u < share; u += 4) {
+                const ulonglong2 a2 = *reinterpret_cast<const ulonglong2*>(&part[u]);
+                const ulonglong2 b2 = *reinterpret_cast<const ulonglong2*>(&part[u + 2]);
                 r += (a2.x < mine ? 1 : 0) + (a2.y < mine ? 1 : 0) + (b2.x < mine ? 1 : 0) +
                      (b2.y < mine ? 1 : 0);
             }
+            if (gsz <= 32) r += __shfl_xor(r, 32);
+            if (gsz <= 16) r += __shfl_xor(r, 16);
             const int len = state == kRowFull ? k : cnt;
             if (lane < cnt && r < len) {
                 const long long o = (long long)k * qid + r;
