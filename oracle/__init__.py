@@ -10,7 +10,8 @@ starting from the same FP32 arrays the GPU receives.  The normalisation
 helpers below (RDF, PMF, PMFT, smoothed RDF) are closed-form FP64 numpy.
 
 Each function names the part of the paper it follows.  Parity status:
-  * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts,
+  * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts, the 2D
+    PMFT with relative orientation (XYT) and the 3D PMFT (XYZ) counts,
     smoothed RDF and its gradient: pinned (see tests/test_oracle_*.py);
   * RDF / PMFT normalisation constants: the paper defines the PMF and PMFT
     only up to an additive constant, so the convention below is a reading,
@@ -65,6 +66,10 @@ def lib():
             "orc_rdf": [BP, P, i64, P, i64, i64, f64, f64, i32, f64, P, P, P],
             "orc_knn": [BP, P, i64, P, i64, i32, i32, i32, f64, P, P, P],
             "orc_pmft2d": [BP, P, i64, P, P, i64, i64, i64, f64, f64, f64, i32, f64, f64, P, P, P],
+            "orc_pmft_xyt": [BP, P, P, i64, P, P, i64, i64, i64, i64, f64, f64, f64, i32, f64,
+                             f64, f64, P, P, P],
+            "orc_pmft_xyz": [BP, P, i64, P, P, i64, i64, i64, i64, f64, f64, f64, f64, i32, f64,
+                             f64, P, P, P],
             "orc_smooth_rdf": [BP, P, i64, i64, f64, f64, P],
             "orc_smooth_rdf_row": [BP, P, i64, i64, P, i64, f64, f64, P],
             "orc_smooth_rdf_grad": [BP, P, i64, i64, f64, f64, P, P, i64, P],
@@ -186,6 +191,56 @@ def pmft2d_counts(box: Box, points, query_points, query_theta, nbx: int, nby: in
     return lo.reshape(nbx, nby), hi.reshape(nbx, nby), int(amb[0])
 
 
+def pmft_xyt_counts(box: Box, points, theta, query_points, query_theta, nbx: int, nby: int,
+                    nbt: int, x_max: float, y_max: float, r_max: float, exclude_ii=None,
+                    rel_band: float = REL_BAND, abs_band=None, t_band=None):
+    """2D PMFT with relative orientation (PMFT section): bounds (lo, hi,
+    n_ambiguous) of counts[ix, iy, it] over (x', y', (theta_j - theta_i) mod 2pi)."""
+    pts = _f32(points)
+    same = query_points is None
+    if exclude_ii is None:
+        exclude_ii = same
+    q = pts if same else _f32(query_points)
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    qth = th if same and query_theta is None else np.ascontiguousarray(query_theta, np.float32)
+    if abs_band is None:
+        abs_band = rel_band * max(x_max, y_max)
+    if t_band is None:
+        t_band = rel_band * 2.0 * math.pi
+    nb = nbx * nby * nbt
+    lo = np.zeros(nb, np.uint64)
+    hi = np.zeros(nb, np.uint64)
+    amb = np.zeros(1, np.uint64)
+    lib().orc_pmft_xyt(ctypes.byref(box), _p(pts), _p(th), pts.shape[0], _p(q), _p(qth),
+                       q.shape[0], nbx, nby, nbt, float(x_max), float(y_max), float(r_max),
+                       int(exclude_ii), rel_band, float(abs_band), float(t_band), _p(lo), _p(hi),
+                       _p(amb))
+    return lo.reshape(nbx, nby, nbt), hi.reshape(nbx, nby, nbt), int(amb[0])
+
+
+def pmft_xyz_counts(box: Box, points, query_points, query_quat, nbx: int, nby: int, nbz: int,
+                    x_max: float, y_max: float, z_max: float, r_max: float, exclude_ii=None,
+                    rel_band: float = REL_BAND, abs_band=None):
+    """3D PMFT (PMFT section): bounds (lo, hi, n_ambiguous) of counts[ix, iy, iz]
+    of the bonds in the frame of each query's unit quaternion (w, x, y, z)."""
+    pts = _f32(points)
+    same = query_points is None
+    if exclude_ii is None:
+        exclude_ii = same
+    q = pts if same else _f32(query_points)
+    qq = np.ascontiguousarray(query_quat, dtype=np.float32).reshape(-1, 4)
+    if abs_band is None:
+        abs_band = rel_band * max(x_max, y_max, z_max)
+    nb = nbx * nby * nbz
+    lo = np.zeros(nb, np.uint64)
+    hi = np.zeros(nb, np.uint64)
+    amb = np.zeros(1, np.uint64)
+    lib().orc_pmft_xyz(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), _p(qq), q.shape[0], nbx,
+                       nby, nbz, float(x_max), float(y_max), float(z_max), float(r_max),
+                       int(exclude_ii), rel_band, float(abs_band), _p(lo), _p(hi), _p(amb))
+    return lo.reshape(nbx, nby, nbz), hi.reshape(nbx, nby, nbz), int(amb[0])
+
+
 def smooth_rdf_h(box: Box, points, bins: int, r_max: float, sigma: float):
     """Smoothed RDF numerator h_b (FP64) over all ordered pairs."""
     pts = _f32(points)
@@ -261,6 +316,28 @@ def pmft2d_from_counts(counts, n_points, n_query, area, x_max, y_max, n_frames=1
     nbx, nby = counts.shape
     dxdy = (2 * x_max / nbx) * (2 * y_max / nby)
     pcf = counts / (n_frames * n_query * (n_points / area) * dxdy)
+    with np.errstate(divide="ignore"):
+        return -np.log(pcf)
+
+
+def pmft_xyt_from_counts(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
+    """beta F(x, y, t) = -ln(counts / (N_q rho dx dy (dt / 2 pi) frames)): the
+    relative orientation is weighted by its share of the full turn, so an
+    ideal gas gives F = 0; +inf at 0."""
+    counts = np.asarray(counts, np.float64)
+    nbx, nby, nbt = counts.shape
+    w = (2 * x_max / nbx) * (2 * y_max / nby) / nbt
+    pcf = counts / (n_frames * n_query * (n_points / area) * w)
+    with np.errstate(divide="ignore"):
+        return -np.log(pcf)
+
+
+def pmft_xyz_from_counts(counts, n_points, n_query, volume, x_max, y_max, z_max, n_frames=1):
+    """beta F(x, y, z) = -ln(counts / (N_q rho dx dy dz frames)); +inf at 0."""
+    counts = np.asarray(counts, np.float64)
+    nbx, nby, nbz = counts.shape
+    w = (2 * x_max / nbx) * (2 * y_max / nby) * (2 * z_max / nbz)
+    pcf = counts / (n_frames * n_query * (n_points / volume) * w)
     with np.errstate(divide="ignore"):
         return -np.log(pcf)
 

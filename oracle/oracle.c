@@ -1,6 +1,7 @@
 /*
- * FP64 reference oracle for periodic neighbor queries, the RDF, the 2D PMFT
- * and a Gaussian-smoothed RDF with its gradient.
+ * FP64 reference oracle for periodic neighbor queries, the RDF, the 2D PMFT,
+ * the 2D PMFT with relative orientation and the 3D PMFT, and a
+ * Gaussian-smoothed RDF with its gradient.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
  * graded against.  Only the test suite, the smoke check and the CPU-baseline
@@ -322,6 +323,172 @@ int orc_pmft2d(const orc_box* b, const float* pts, int64_t n, const float* q, co
                         for (int64_t iy = iy0; iy <= iy1; ++iy)
                             if (ix >= 0 && ix < nbx && iy >= 0 && iy < nby) thi[ix * nby + iy]++;
                 }
+            }
+        }
+#pragma omp critical
+        {
+            for (int64_t t = 0; t < nbins; ++t) { lo[t] += tlo[t]; hi[t] += thi[t]; }
+            amb_total += tamb;
+        }
+        free(tlo);
+        free(thi);
+    }
+    *n_amb = amb_total;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Three-dimensional PMFT histograms (PMFT section: in 2D the full PMFT also
+ * resolves the orientation of the second particle relative to the first; in
+ * 3D the translational part alone is three-dimensional).  Both bin the bond
+ * d = minimum image of p_j - q_i of every pair closer than r_max, seen from
+ * the query particle's own frame, in a uniform histogram:
+ *
+ *   XYT (2D): (x', y') = R(-theta_i) d as in the 2D PMFT, and the relative
+ *     orientation t = (theta_j - theta_i) mod 2 pi in [0, 2 pi), binned into
+ *     nbt equal bins; counts[(ix * nby + iy) * nbt + it].
+ *   XYZ (3D): d' = R(q_i)^T d, the bond in the frame of the query's unit
+ *     quaternion q_i = (w, x, y, z) (normalised here), with the rotation
+ *     matrix of a unit quaternion; counts[(ix * nby + iy) * nbz + iz] on
+ *     [-x_max, x_max) x [-y_max, y_max) x [-z_max, z_max).
+ *
+ * lo/hi bound the histogram over the ambiguous pairs exactly as in the 2D
+ * PMFT: a pair within rel_band of r_max^2, or within the absolute band of a
+ * bin edge in any coordinate (t_band for the angle, whose edges wrap), adds
+ * 1 to hi in every bin it may reach and is counted in n_amb.  Pinned by:
+ * theta = 0 (XYT) and identity quaternions (XYZ) reducing to numpy's
+ * histogramdd of minimum-image displacements, the marginal over t equal to
+ * the 2D PMFT, hand-computed bins of a two-particle system with a general
+ * angle and a general quaternion, and rotations about z in 3D matching the
+ * 2D PMFT.
+ * ---------------------------------------------------------------------- */
+static void bins3_add(uint64_t* tlo, uint64_t* thi, uint64_t* tamb, int certain,
+                      const int64_t b0[3], const int64_t b1[3], const int64_t nb[3], int wrap2)
+{
+    if (certain && b0[0] == b1[0] && b0[1] == b1[1] && b0[2] == b1[2]) {
+        int64_t k2 = b0[2];
+        if (wrap2) k2 = ((k2 % nb[2]) + nb[2]) % nb[2];
+        if (b0[0] >= 0 && b0[0] < nb[0] && b0[1] >= 0 && b0[1] < nb[1] && k2 >= 0 && k2 < nb[2]) {
+            const int64_t t = (b0[0] * nb[1] + b0[1]) * nb[2] + k2;
+            tlo[t]++;
+            thi[t]++;
+        }
+        return;
+    }
+    ++*tamb;
+    for (int64_t i0 = b0[0]; i0 <= b1[0]; ++i0) {
+        if (i0 < 0 || i0 >= nb[0]) continue;
+        for (int64_t i1 = b0[1]; i1 <= b1[1]; ++i1) {
+            if (i1 < 0 || i1 >= nb[1]) continue;
+            for (int64_t i2 = b0[2]; i2 <= b1[2]; ++i2) {
+                int64_t k2 = i2;
+                if (wrap2) k2 = ((k2 % nb[2]) + nb[2]) % nb[2];
+                if (k2 < 0 || k2 >= nb[2]) continue;
+                thi[(i0 * nb[1] + i1) * nb[2] + k2]++;
+            }
+        }
+    }
+}
+
+int orc_pmft_xyt(const orc_box* b, const float* pts, const float* theta, int64_t n,
+                 const float* q, const float* q_theta, int64_t nq, int64_t nbx, int64_t nby,
+                 int64_t nbt, double x_max, double y_max, double r_max, int32_t exclude_ii,
+                 double rel_band, double abs_band, double t_band, uint64_t* lo, uint64_t* hi,
+                 uint64_t* n_amb)
+{
+    const double two_pi = 2.0 * M_PI;
+    const double w[3] = {2.0 * x_max / (double)nbx, 2.0 * y_max / (double)nby,
+                         two_pi / (double)nbt};
+    const double org[3] = {-x_max, -y_max, 0.0};
+    const int64_t nb[3] = {nbx, nby, nbt};
+    const double r2_in = r_max * r_max * (1.0 - rel_band);
+    const double r2_lim = r_max * r_max * (1.0 + rel_band);
+    const int64_t nbins = nbx * nby * nbt;
+    memset(lo, 0, sizeof(uint64_t) * nbins);
+    memset(hi, 0, sizeof(uint64_t) * nbins);
+    uint64_t amb_total = 0;
+#pragma omp parallel
+    {
+        uint64_t* tlo = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+        uint64_t* thi = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+        uint64_t tamb = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nq; ++i) {
+            const double th = (double)q_theta[i];
+            const double c = cos(th), s = sin(th);
+            double d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                if (exclude_ii && i == j) continue;
+                const double r2 = pair_r2(b, pts + 3 * j, q + 3 * i, d);
+                if (r2 >= r2_lim) continue;
+                double t = fmod((double)theta[j] - th, two_pi);
+                if (t < 0.0) t += two_pi;
+                const double v[3] = {c * d[0] + s * d[1], -s * d[0] + c * d[1], t};
+                const double band[3] = {abs_band, abs_band, t_band};
+                int64_t b0[3], b1[3];
+                for (int k = 0; k < 3; ++k) {
+                    b0[k] = (int64_t)floor((v[k] - band[k] - org[k]) / w[k]);
+                    b1[k] = (int64_t)floor((v[k] + band[k] - org[k]) / w[k]);
+                }
+                bins3_add(tlo, thi, &tamb, r2 < r2_in, b0, b1, nb, 1);
+            }
+        }
+#pragma omp critical
+        {
+            for (int64_t t = 0; t < nbins; ++t) { lo[t] += tlo[t]; hi[t] += thi[t]; }
+            amb_total += tamb;
+        }
+        free(tlo);
+        free(thi);
+    }
+    *n_amb = amb_total;
+    return 0;
+}
+
+int orc_pmft_xyz(const orc_box* b, const float* pts, int64_t n, const float* q,
+                 const float* q_quat, int64_t nq, int64_t nbx, int64_t nby, int64_t nbz,
+                 double x_max, double y_max, double z_max, double r_max, int32_t exclude_ii,
+                 double rel_band, double abs_band, uint64_t* lo, uint64_t* hi, uint64_t* n_amb)
+{
+    const double w[3] = {2.0 * x_max / (double)nbx, 2.0 * y_max / (double)nby,
+                         2.0 * z_max / (double)nbz};
+    const double org[3] = {-x_max, -y_max, -z_max};
+    const int64_t nb[3] = {nbx, nby, nbz};
+    const double r2_in = r_max * r_max * (1.0 - rel_band);
+    const double r2_lim = r_max * r_max * (1.0 + rel_band);
+    const int64_t nbins = nbx * nby * nbz;
+    memset(lo, 0, sizeof(uint64_t) * nbins);
+    memset(hi, 0, sizeof(uint64_t) * nbins);
+    uint64_t amb_total = 0;
+#pragma omp parallel
+    {
+        uint64_t* tlo = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+        uint64_t* thi = (uint64_t*)calloc((size_t)nbins, sizeof(uint64_t));
+        uint64_t tamb = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nq; ++i) {
+            /* rotation matrix of the normalised quaternion (w, x, y, z) */
+            double qw = q_quat[4 * i], qx = q_quat[4 * i + 1], qy = q_quat[4 * i + 2],
+                   qz = q_quat[4 * i + 3];
+            const double nrm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            qw /= nrm; qx /= nrm; qy /= nrm; qz /= nrm;
+            const double R[3][3] = {
+                {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy)},
+                {2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx)},
+                {2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
+            double d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                if (exclude_ii && i == j) continue;
+                const double r2 = pair_r2(b, pts + 3 * j, q + 3 * i, d);
+                if (r2 >= r2_lim) continue;
+                int64_t b0[3], b1[3];
+                for (int k = 0; k < 3; ++k) {
+                    /* row k of R^T is column k of R */
+                    const double v = R[0][k] * d[0] + R[1][k] * d[1] + R[2][k] * d[2];
+                    b0[k] = (int64_t)floor((v - abs_band - org[k]) / w[k]);
+                    b1[k] = (int64_t)floor((v + abs_band - org[k]) / w[k]);
+                }
+                bins3_add(tlo, thi, &tamb, r2 < r2_in, b0, b1, nb, 0);
             }
         }
 #pragma omp critical

@@ -28,6 +28,7 @@ class System:
     dim: int
     points: np.ndarray          # float32 [N, 3]
     theta: np.ndarray | None = None  # float32 [N] orientations (2D)
+    quat: np.ndarray | None = None   # float32 [N, 4] unit quaternions (w, x, y, z) (3D)
 
 
 def lattice_vectors(L, tilt, dim=3):
@@ -140,6 +141,19 @@ def fluid_2d(seed=1003, n=262144, density=0.7):
     r = _from_fractional(s, L, (0.0, 0.0, 0.0), 2)
     theta = rng.uniform(0.0, 2.0 * math.pi, size=n)
     return System(L, (0.0, 0.0, 0.0), 2, _finish(r), np.ascontiguousarray(theta, np.float32))
+
+
+def fluid_3d(seed=1007, n=262144, density=0.9, tilt=(0.0, 0.0, 0.0)):
+    """3D uniform points with orientations as unit quaternions (w, x, y, z)
+    uniform over rotations (normalised Gaussian 4-vectors)."""
+    rng = np.random.default_rng(seed)
+    side = (n / density) ** (1.0 / 3.0)
+    L = (side, side, side)
+    s = rng.uniform(-0.5, 0.5, size=(n, 3))
+    r = _from_fractional(s, L, tilt, 3)
+    g = rng.normal(size=(n, 4))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return System(L, tuple(tilt), 3, _finish(r), None, np.ascontiguousarray(g, np.float32))
 
 
 def trajectory(seed=1004, frames=256, n_lo=1000, n_hi=200000):
