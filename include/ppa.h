@@ -190,6 +190,66 @@ int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpt
                float y_max, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
                size_t ws_bytes, uint32_t* counts, hipStream_t stream);
 
+/* Workspace bytes for ppa_pmft_xyt / ppa_pmft_xyz with these arguments (nq:
+ * separate query points, 0 when the points query themselves): the cell
+ * lists of the points (and queries).  No device work.  Same error codes as
+ * the calls' host checks. */
+int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
+                                 int32_t nby, int32_t nbt, float x_max, float y_max, float r_max,
+                                 size_t* bytes);
+int ppa_pmft_xyz_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
+                                 int32_t nby, int32_t nbz, float x_max, float y_max, float z_max,
+                                 float r_max, size_t* bytes);
+
+/* 2D PMFT with the relative orientation (the paper's PMFT section: in 2D
+ * the full PMFT is three-dimensional, since the second particle's
+ * orientation relative to the first is a coordinate too).  For every ball
+ * pair (i, j) as in ppa_pmft2d, (x', y') is the bond in the query's frame
+ * exactly as there, and t = (theta_j - theta_i) mod 2 pi in [0, 2 pi).  The
+ * bond is counted in bin (ix, iy, it), it = floor(t nbt / (2 pi)), when ix
+ * and iy lie in range (t always does):
+ *     counts[(ix * nby + iy) * nbt + it] += the count (uint32, device,
+ *     accumulated; it wraps past 2^32).
+ *   box: dim must be 2 (PPA_EINVAL otherwise).
+ *   pts [n x 3], qpts [nq x 3] or NULL, exclude_ii: as for ppa_query_ball.
+ *   angles [n] float32 device: orientation of every point in radians.
+ *   qangles [nq] float32 device: orientation of every query point (ignored,
+ *     and may be NULL, when qpts is NULL: the points' angles are used).
+ *   nbx, nby, nbt >= 1 (product below 2^31); x_max, y_max > 0; r_max below
+ *     half the smallest width.
+ *   flags: reserved, must be 0.
+ * Non-finite angles set PPA_ENONFINITE in the device status.  Bonds go to
+ * the histogram with global atomics: it may be of any size. */
+int ppa_pmft_xyt(const ppa_box* box, const float* pts, const float* angles, int64_t n,
+                 const float* qpts, const float* qangles, int64_t nq, int32_t nbx, int32_t nby,
+                 int32_t nbt, float x_max, float y_max, float r_max, int32_t exclude_ii,
+                 int32_t flags, void* ws, size_t ws_bytes, uint32_t* counts, hipStream_t stream);
+
+/* 3D PMFT over the bond's position in the query particle's frame (the
+ * paper's PMFT section: the translational degrees of freedom of a 3D
+ * PMFT).  For every ball pair (i, j), |p_j - q_i| < r_max (minimum image),
+ * excluding j == i when exclude_ii is set, the bond d = p_j - q_i is turned
+ * into the query's frame, d' = R(q_i)^T d, with R the rotation matrix of the
+ * query's unit quaternion q_i = (w, x, y, z), and counted in bin
+ * (ix, iy, iz) = floor((d' + max) nb / (2 max)) per axis when all three lie
+ * in range:
+ *     counts[(ix * nby + iy) * nbz + iz] += the count (uint32, device,
+ *     accumulated; it wraps past 2^32).
+ *   box: dim must be 3 (PPA_EINVAL otherwise).
+ *   pts [n x 3], qpts [nq x 3] or NULL, exclude_ii: as for ppa_query_ball.
+ *   qquats [nq x 4] float32 device, 16-byte aligned: orientation of every
+ *     query point (of pts when qpts is NULL) as a quaternion (w, x, y, z);
+ *     each is normalised first.
+ *   nbx, nby, nbz >= 1 (product below 2^31); x_max, y_max, z_max > 0;
+ *     r_max below half the smallest perpendicular width.
+ *   flags: reserved, must be 0.
+ * A zero or non-finite quaternion sets PPA_ENONFINITE in the device
+ * status.  Bonds go to the histogram with global atomics. */
+int ppa_pmft_xyz(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
+                 const float* qquats, int64_t nq, int32_t nbx, int32_t nby, int32_t nbz,
+                 float x_max, float y_max, float z_max, float r_max, int32_t exclude_ii,
+                 int32_t flags, void* ws, size_t ws_bytes, uint32_t* counts, hipStream_t stream);
+
 /* Gaussian-smoothed RDF (an extension beyond the paper: a differentiable
  * form of the density module's RDF histogram).  With bins of width
  * dr = r_max / bins centred at c_b = (b + 1/2) dr and

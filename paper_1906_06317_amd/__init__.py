@@ -111,6 +111,14 @@ def lib():
             "ppa_pmft2d_workspace_bytes": [BP, i64, i64, i32, i32, f32, f32, f32,
                                            ctypes.POINTER(sz)],
             "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
+            "ppa_pmft_xyt_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32,
+                                             ctypes.POINTER(sz)],
+            "ppa_pmft_xyt": [BP, P, P, i64, P, P, i64, i32, i32, i32, f32, f32, f32, i32, i32, P,
+                             sz, P, P],
+            "ppa_pmft_xyz_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32, f32,
+                                             ctypes.POINTER(sz)],
+            "ppa_pmft_xyz": [BP, P, i64, P, P, i64, i32, i32, i32, f32, f32, f32, f32, i32, i32,
+                             P, sz, P, P],
             "ppa_smooth_rdf_workspace_bytes": [BP, i64, i32, f32, f32, ctypes.POINTER(sz)],
             "ppa_batch_plan_create": [i32, BP, P, i32, f32, f32, i32, i32,
                                       ctypes.POINTER(ctypes.c_void_p)],
@@ -414,6 +422,126 @@ def normalize_pmft2d(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
     nbx, nby = c.shape
     dxdy = (2.0 * x_max / nbx) * (2.0 * y_max / nby)
     pcf = c / (n_frames * n_query * (n_points / area) * dxdy)
+    with np.errstate(divide="ignore"):
+        pmft = -np.log(pcf)
+    return pcf, pmft
+
+
+def _orient(v, device, rows, width, what):
+    torch = _torch()
+    t = v if isinstance(v, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(v, np.float32))
+    t = t.to(device=device, dtype=torch.float32).contiguous().reshape(-1)
+    if t.shape[0] != rows * width:
+        raise ValueError(f"one {what} per point is required")
+    return t
+
+
+def pmft_xyt_workspace_bytes(box: Box, n, nq, nbx, nby, nbt, x_max, y_max, r_max):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_pmft_xyt_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), int(nbx),
+                                              int(nby), int(nbt), float(x_max), float(y_max),
+                                              float(r_max), ctypes.byref(out)))
+    return out.value
+
+
+def pmft_xyt_counts(box: Box, points, angles, nbx, nby, nbt, x_max, y_max, r_max,
+                    query_points=None, query_angles=None, exclude_ii=None, counts=None, ws=None,
+                    stream=None, check=True):
+    """2D PMFT with relative orientation, uint32 [nbx, nby, nbt] over
+    (x', y', (theta_j - theta_i) mod 2 pi), accumulated into `counts`.
+
+    `angles` are the points' orientations; `query_angles` those of the query
+    points (needed only with query_points)."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    th = _orient(angles, pts.device, n, 1, "orientation")
+    qth = None
+    if q is not None:
+        if query_angles is None:
+            raise ValueError("query_angles are required with query_points")
+        qth = _orient(query_angles, pts.device, nq, 1, "orientation")
+    if counts is None:
+        counts = torch.zeros((int(nbx), int(nby), int(nbt)), dtype=torch.uint32, device=pts.device)
+    if nq == 0:
+        return counts
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(pmft_xyt_workspace_bytes(box, n, 0 if q is None else nq, nbx, nby, nbt,
+                                                 x_max, y_max, r_max))
+    _check(lib().ppa_pmft_xyt(ctypes.byref(box.c()), _ptr(pts), _ptr(th), n, _ptr(q), _ptr(qth),
+                              nq, int(nbx), int(nby), int(nbt), float(x_max), float(y_max),
+                              float(r_max), int(bool(exclude_ii)), 0, wptr, wlen, _ptr(counts),
+                              _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return counts
+
+
+def normalize_pmft_xyt(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
+    """(pair correlation, PMFT) from XYT counts, float64 on the host:
+    pcf = counts / (n_frames N_q rho dx dy (dt / 2 pi)) with rho = N_p / area,
+    so an ideal gas gives 1; PMFT = -ln(pcf) (+inf where a bin is empty)."""
+    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
+    nbx, nby, nbt = c.shape
+    w = (2.0 * x_max / nbx) * (2.0 * y_max / nby) / nbt
+    pcf = c / (n_frames * n_query * (n_points / area) * w)
+    with np.errstate(divide="ignore"):
+        pmft = -np.log(pcf)
+    return pcf, pmft
+
+
+def pmft_xyz_workspace_bytes(box: Box, n, nq, nbx, nby, nbz, x_max, y_max, z_max, r_max):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_pmft_xyz_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), int(nbx),
+                                              int(nby), int(nbz), float(x_max), float(y_max),
+                                              float(z_max), float(r_max), ctypes.byref(out)))
+    return out.value
+
+
+def pmft_xyz_counts(box: Box, points, quats, nbx, nby, nbz, x_max, y_max, z_max, r_max,
+                    query_points=None, exclude_ii=None, counts=None, ws=None, stream=None,
+                    check=True):
+    """3D PMFT bond histogram, uint32 [nbx, nby, nbz] of the bonds in each
+    query's frame, accumulated into `counts`.
+
+    `quats` [nq, 4] are the orientations (w, x, y, z) of the query points
+    (of `points` when query_points is None)."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    qq = _orient(quats, pts.device, nq, 4, "quaternion")
+    if counts is None:
+        counts = torch.zeros((int(nbx), int(nby), int(nbz)), dtype=torch.uint32, device=pts.device)
+    if nq == 0:
+        return counts
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(pmft_xyz_workspace_bytes(box, n, 0 if q is None else nq, nbx, nby, nbz,
+                                                 x_max, y_max, z_max, r_max))
+    _check(lib().ppa_pmft_xyz(ctypes.byref(box.c()), _ptr(pts), n, _ptr(q), _ptr(qq), nq,
+                              int(nbx), int(nby), int(nbz), float(x_max), float(y_max),
+                              float(z_max), float(r_max), int(bool(exclude_ii)), 0, wptr, wlen,
+                              _ptr(counts), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return counts
+
+
+def normalize_pmft_xyz(counts, n_points, n_query, volume, x_max, y_max, z_max, n_frames=1):
+    """(pair correlation, PMFT) from XYZ counts, float64 on the host:
+    pcf = counts / (n_frames N_q rho dx dy dz), rho = N_p / volume;
+    PMFT = -ln(pcf) (+inf where a bin is empty)."""
+    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
+    nbx, nby, nbz = c.shape
+    w = (2.0 * x_max / nbx) * (2.0 * y_max / nby) * (2.0 * z_max / nbz)
+    pcf = c / (n_frames * n_query * (n_points / volume) * w)
     with np.errstate(divide="ignore"):
         pmft = -np.log(pcf)
     return pcf, pmft

@@ -615,6 +615,118 @@ int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
 }
 
 // ---------------------------------------------------------------------------
+// PMFT over three pair coordinates (XYT in 2D, XYZ in 3D): validation,
+// workspace (the cell lists alone) and launch.
+// ---------------------------------------------------------------------------
+struct Pmft3Call {
+    int mode;
+    const ppa_box* box;
+    const float* pts;
+    const float* p_orient;
+    int64_t n;
+    const float* qpts;
+    const float* q_orient;
+    int64_t nq;
+    int32_t nb[3];
+    float max[3];
+    float r_max;
+};
+
+int pmft3_check(const Pmft3Call& c, BoxPrep* bp, Grid* g)
+{
+    const int dim = c.mode == kPmftXyt ? 2 : 3;
+    if (c.n < 0 || c.nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (c.n > 0x7fffffffLL || c.nq > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "point counts are limited to 2^31 - 1");
+    const int64_t nbins = (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
+    if (c.nb[0] < 1 || c.nb[1] < 1 || c.nb[2] < 1 || nbins > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "bad bin counts %d x %d x %d", c.nb[0], c.nb[1], c.nb[2]);
+    for (int k = 0; k < (dim == 3 ? 3 : 2); ++k)
+        if (!(isfinite(c.max[k]) && c.max[k] > 0.f))
+            return set_error(PPA_EINVAL, "the coordinate ranges must be finite and positive");
+    if (!(isfinite(c.r_max) && c.r_max > 0.f)) return set_error(PPA_EINVAL, "r_max must be positive");
+    int rc = prepare_box(c.box, bp);
+    if (rc) return rc;
+    if (bp->dim != dim)
+        return set_error(PPA_EINVAL, dim == 2 ? "the XYT PMFT needs a 2D box"
+                                              : "the XYZ PMFT needs a 3D box");
+    if ((rc = check_cutoff(*bp, c.r_max))) return rc;
+    pair_grid(*bp, c.r_max, c.n, g);
+    return PPA_OK;
+}
+
+int pmft3_workspace(const Pmft3Call& c, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    BoxPrep bp;
+    Grid g;
+    int rc = pmft3_check(c, &bp, &g);
+    if (rc) return rc;
+    Workspace W{};
+    *bytes = workspace_layout(g, c.n, c.nq, 0, nullptr, &W);
+    return PPA_OK;
+}
+
+int run_pmft3(const Pmft3Call& c, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
+              uint32_t* counts, hipStream_t s)
+{
+    if (!c.pts && c.n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (!c.qpts && c.nq != c.n)
+        return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (!c.q_orient && c.nq > 0) return set_error(PPA_EINVAL, "orientations pointer is NULL");
+    if (c.mode == kPmftXyt && !c.p_orient && c.n > 0)
+        return set_error(PPA_EINVAL, "orientations of the points are NULL");
+    if (c.mode == kPmftXyz && ((uintptr_t)c.q_orient & 15))
+        return set_error(PPA_EINVAL, "quaternions must be 16-byte aligned");
+    if (!counts) return set_error(PPA_EINVAL, "counts pointer is NULL");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    BoxPrep bp;
+    Grid g;
+    int rc = pmft3_check(c, &bp, &g);
+    if (rc) return rc;
+    const int64_t nq_sep = c.qpts ? c.nq : 0;
+    Workspace W{};
+    const size_t need = workspace_layout(g, c.n, nq_sep, 0, nullptr, &W);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    workspace_layout(g, c.n, nq_sep, 0, ws, &W);
+    if (c.nq == 0) return PPA_OK;
+    launch_zero(W, g, c.qpts != nullptr, nullptr, 0, s);
+    launch_build_cells(c.pts, W.pts, bp, g, W.status, s);
+    if (c.qpts) launch_build_cells(c.qpts, W.qry, bp, g, W.status, s);
+
+    Pmft3Args A{};
+    A.cand = W.pts.local;
+    A.cand_start = W.pts.cell_start;
+    A.qsorted = W.qry.local;
+    A.q_start = W.qry.cell_start;
+    A.q_orient = c.q_orient;
+    A.p_orient = c.p_orient;
+    for (int d = 0; d < 3; ++d) A.geom.n[d] = g.n[d];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    A.geom.r2max = c.r_max * c.r_max;
+    A.mode = c.mode;
+    A.excl = exclude_ii ? 1 : 0;
+    for (int k = 0; k < 3; ++k) {
+        A.nb[k] = c.nb[k];
+        A.max[k] = c.max[k];
+        // the angle spans [0, 2 pi); lengths span [-max, max)
+        const double span = (c.mode == kPmftXyt && k == 2) ? 2.0 * M_PI : 2.0 * (double)c.max[k];
+        A.inv_w[k] = (float)((double)c.nb[k] / span);
+    }
+    A.counts = counts;
+    A.status = W.status;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], s);
+    launch_pmft3(A, s);
+    record(pe.ev[3], s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+// ---------------------------------------------------------------------------
 // Gaussian-smoothed RDF: plan, workspace and launches.
 // ---------------------------------------------------------------------------
 struct SmoothPlan {
@@ -867,6 +979,44 @@ int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpt
 {
     return run_pmft(box, pts, n, qpts, angles, nq, nbx, nby, x_max, y_max, r_max, exclude_ii,
                     flags, ws, ws_bytes, counts, stream);
+}
+
+int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
+                                 int32_t nby, int32_t nbt, float x_max, float y_max, float r_max,
+                                 size_t* bytes)
+{
+    const Pmft3Call c{kPmftXyt, box, nullptr, nullptr, n, nullptr, nullptr, nq,
+                      {nbx, nby, nbt}, {x_max, y_max, 1.f}, r_max};
+    return pmft3_workspace(c, bytes);
+}
+
+int ppa_pmft_xyt(const ppa_box* box, const float* pts, const float* angles, int64_t n,
+                 const float* qpts, const float* qangles, int64_t nq, int32_t nbx, int32_t nby,
+                 int32_t nbt, float x_max, float y_max, float r_max, int32_t exclude_ii,
+                 int32_t flags, void* ws, size_t ws_bytes, uint32_t* counts, hipStream_t stream)
+{
+    const Pmft3Call c{kPmftXyt, box, pts, angles, n, qpts, qpts ? qangles : angles, nq,
+                      {nbx, nby, nbt}, {x_max, y_max, 1.f}, r_max};
+    return run_pmft3(c, exclude_ii, flags, ws, ws_bytes, counts, stream);
+}
+
+int ppa_pmft_xyz_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
+                                 int32_t nby, int32_t nbz, float x_max, float y_max, float z_max,
+                                 float r_max, size_t* bytes)
+{
+    const Pmft3Call c{kPmftXyz, box, nullptr, nullptr, n, nullptr, nullptr, nq,
+                      {nbx, nby, nbz}, {x_max, y_max, z_max}, r_max};
+    return pmft3_workspace(c, bytes);
+}
+
+int ppa_pmft_xyz(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
+                 const float* qquats, int64_t nq, int32_t nbx, int32_t nby, int32_t nbz,
+                 float x_max, float y_max, float z_max, float r_max, int32_t exclude_ii,
+                 int32_t flags, void* ws, size_t ws_bytes, uint32_t* counts, hipStream_t stream)
+{
+    const Pmft3Call c{kPmftXyz, box, pts, nullptr, n, qpts, qquats, nq,
+                      {nbx, nby, nbz}, {x_max, y_max, z_max}, r_max};
+    return run_pmft3(c, exclude_ii, flags, ws, ws_bytes, counts, stream);
 }
 
 int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, float r_max,

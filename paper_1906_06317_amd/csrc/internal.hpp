@@ -231,6 +231,29 @@ int pmft_workgroups(int words);
 size_t pmft_lds_limit();  // bytes of LDS a workgroup may give the histogram
 void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s);
 
+// PMFT over three pair coordinates (pmft3.hip): XYT in 2D, XYZ in 3D.
+constexpr int kPmftXyt = 0;
+constexpr int kPmftXyz = 1;
+
+struct Pmft3Args {
+    const float4* cand;       // points sorted by cell
+    const int* cand_start;    // [ncells + 1]
+    const float4* qsorted;    // query points sorted by cell
+    const int* q_start;       // [ncells + 1]
+    const float* q_orient;    // XYT: [nq] angles; XYZ: [nq][4] quaternions (w, x, y, z)
+    const float* p_orient;    // XYT: [n] angles of the points; XYZ: unused
+    PairGeom geom;
+    int mode;                 // kPmftXyt or kPmftXyz
+    int excl;                 // 1: drop the point whose index is the query's
+    int nb[3];                // bins per coordinate
+    float max[3];             // x_max, y_max, z_max (unused for t)
+    float inv_w[3];           // bins per unit of each coordinate
+    unsigned* counts;         // [nb0 * nb1 * nb2] accumulated
+    unsigned* status;         // workspace status word
+};
+
+void launch_pmft3(const Pmft3Args& a, hipStream_t s);
+
 // Gaussian-smoothed RDF and its adjoint (smooth.hip).
 constexpr int kSmoothMaxBins = 4096;
 
