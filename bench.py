@@ -355,6 +355,75 @@ def lds_atomic_peak(ppa):
     return res
 
 
+def global_atomic_peak(ppa):
+    """Global-memory atomic adds per second of the device (microbenchmark,
+    random words of a histogram of 2^17 and 2^19 words)."""
+    import torch
+    L = ppa.lib()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for lw in (17, 19):
+        hist = torch.zeros(1 << lw, dtype=torch.int32, device="cuda")
+        blocks, iters = 2048, 16
+        ms = timed(lambda: L.ppa_probe_global_atomics(lw, iters, blocks,
+                                                      ctypes.c_void_p(hist.data_ptr()), sptr), 5)
+        res[f"{1 << lw}_words_per_s"] = blocks * 256 * 8 * iters / (ms * 1e-3)
+    return res
+
+
+def row_pmft3(ppa, hip, peak):
+    """PMFT over three pair coordinates: XYT on the 2D fluid, XYZ on a 3D fluid."""
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    out = {}
+    s = workloads.fluid_2d()
+    s3 = workloads.fluid_3d()
+    cases = {
+        "xyt": (s, (100, 100, 36), "2D fluid N=262,144, density 0.7, orientations uniform; "
+                "r_max=3, 100x100x36 bins over (x', y') in [-3,3)^2 and t in [0, 2 pi)"),
+        "xyz": (s3, (50, 50, 50), "3D fluid N=262,144, density 0.9, unit quaternions uniform "
+                "over rotations; r_max=2, 50^3 bins on [-2,2)^3"),
+    }
+    for name, (sys_, nb, desc) in cases.items():
+        box = ppa.Box(sys_.L, sys_.tilt, sys_.dim)
+        n = sys_.points.shape[0]
+        pts = torch.as_tensor(sys_.points).cuda()
+        counts = torch.zeros(nb, dtype=torch.uint32, device="cuda")
+        if name == "xyt":
+            th = torch.as_tensor(sys_.theta).cuda()
+            fn = lambda: ppa.pmft_xyt_counts(box, pts, th, *nb, 3.0, 3.0, 3.0, counts=counts,
+                                             check=False)
+            r_max = 3.0
+        else:
+            qq = torch.as_tensor(sys_.quat).cuda()
+            fn = lambda: ppa.pmft_xyz_counts(box, pts, qq, *nb, 2.0, 2.0, 2.0, 2.0, counts=counts,
+                                             check=False)
+            r_max = 2.0
+        evs = []
+
+        def call():
+            e = hip.events(2)
+            evs.append(e)
+            L.ppa_profile_next(None, None, e[0], e[1])
+            fn()
+        ms = timed(call, 10, warmup=2)
+        kern = float(np.mean([hip.ms(e[0], e[1]) for e in evs[2:]]))
+        for e in evs:
+            hip.destroy(e)
+        if ppa.default_workspace().status() != 0:
+            raise RuntimeError(L.ppa_last_error().decode())
+        pairs = ppa.query_ball(box, pts, r_max, with_dist=False).n_pairs
+        ref = peak["131072_words_per_s"] if name == "xyz" else peak["524288_words_per_s"]
+        out[name] = {"workload": desc, "ms": ms, "binning_kernel_ms": kern, "pairs": pairs,
+                     "pairs_per_s": pairs / (ms * 1e-3),
+                     "binning_global_atomics_per_s": pairs / (kern * 1e-3),
+                     "frac_of_global_atomic_probe": pairs / (kern * 1e-3) / ref}
+    return out
+
+
 def row_pmft(ppa, hip):
     import numpy as np
     import torch
@@ -546,6 +615,9 @@ def main():
             rows["pmft2d"]["binning_kernels_ms"] * 1e-3)
         rows["pmft2d"]["frac_of_lds_atomic_probe"] = (
             rows["pmft2d"]["binning_lds_atomics_per_s"] / peak["16384_bins_per_s"])
+        gpeak = global_atomic_peak(ppa)
+        rows["global_atomic_probe"] = gpeak
+        rows["pmft3"] = row_pmft3(ppa, hip, gpeak)
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
         rows["paper_context"] = paper_context(ppa)

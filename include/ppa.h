@@ -379,6 +379,16 @@ int ppa_profile_next(hipEvent_t count_start, hipEvent_t count_stop, hipEvent_t f
 int ppa_probe_lds_atomics(int32_t log2_bins, int32_t iters, int32_t blocks, uint32_t* out_dev,
                           hipStream_t stream);
 
+/* Measurement hook: launches `blocks` workgroups of 256 threads that each
+ * add 1 (32-bit atomics without return value) to pseudo-random words of
+ * hist_dev[0 .. 2^log2_words - 1] (uint32 device, accumulated; the caller
+ * provides 2^log2_words words), 8 x iters atomics per thread (log2_words in
+ * [1, 28]).  Timed by the caller, it gives the device's global atomic rate
+ * for a histogram of that size, the reference for the kernels that bin into
+ * device memory. */
+int ppa_probe_global_atomics(int32_t log2_words, int32_t iters, int32_t blocks,
+                             uint32_t* hist_dev, hipStream_t stream);
+
 /* Waits for the stream and returns the device status of the last call that
  * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE or, for a
  * k-nearest query, PPA_ERANGE). */

@@ -137,6 +137,7 @@ def lib():
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
             "ppa_probe_lds_atomics": [i32, i32, i32, P, P],
+            "ppa_probe_global_atomics": [i32, i32, i32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
