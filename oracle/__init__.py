@@ -11,8 +11,9 @@ helpers below (RDF, PMF, PMFT, smoothed RDF) are closed-form FP64 numpy.
 
 Each function names the part of the paper it follows.  Parity status:
   * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts, the 2D
-    PMFT with relative orientation (XYT) and the 3D PMFT (XYZ) counts,
-    smoothed RDF and its gradient: pinned (see tests/test_oracle_*.py);
+    PMFT with relative orientation (XYT) and the 3D PMFT (XYZ) counts, the
+    spatial correlation function, smoothed RDF and its gradient: pinned
+    (see tests/test_oracle_*.py);
   * RDF / PMFT normalisation constants: the paper defines the PMF and PMFT
     only up to an additive constant, so the convention below is a reading,
     pinned statistically by the ideal-gas limit only.
@@ -66,6 +67,7 @@ def lib():
             "orc_rdf": [BP, P, i64, P, i64, i64, f64, f64, i32, f64, P, P, P],
             "orc_knn": [BP, P, i64, P, i64, i32, i32, i32, f64, P, P, P],
             "orc_pmft2d": [BP, P, i64, P, P, i64, i64, i64, f64, f64, f64, i32, f64, f64, P, P, P],
+            "orc_correlation": [BP, P, P, i64, P, P, i64, i64, f64, f64, i32, f64, P, P, P, P, P],
             "orc_pmft_xyt": [BP, P, P, i64, P, P, i64, i64, i64, i64, f64, f64, f64, i32, f64,
                              f64, f64, P, P, P],
             "orc_pmft_xyz": [BP, P, i64, P, P, i64, i64, i64, i64, f64, f64, f64, f64, i32, f64,
@@ -152,6 +154,43 @@ def rdf_counts(box: Box, points, bins: int, r_max: float, r_min: float = 0.0,
     lib().orc_rdf(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], bins,
                   float(r_min), float(r_max), int(exclude_ii), rel_band, _p(lo), _p(hi), _p(amb))
     return lo, hi, int(amb[0])
+
+
+def _complex_pairs(v, n):
+    v = np.asarray(v)
+    if np.iscomplexobj(v):
+        out = np.stack([v.real, v.imag], -1)
+    else:
+        out = np.asarray(v, np.float64).reshape(n, -1)
+        if out.shape[1] == 1:
+            out = np.concatenate([out, np.zeros_like(out)], 1)
+    return np.ascontiguousarray(out.reshape(n, 2), dtype=np.float32)
+
+
+def correlation(box: Box, points, values, bins: int, r_max: float, r_min: float = 0.0,
+                query_points=None, query_values=None, exclude_ii=None,
+                rel_band: float = REL_BAND):
+    """Spatial correlation function (density module): for ball pairs binned in
+    r, S_b = sum of conj(f_i) g_j (complex128) over certain pairs, the
+    ambiguity mass per bin, count bounds lo/hi and the ambiguous-pair count.
+    Values are complex (or real) per point; query values default to the
+    points' values."""
+    pts = _f32(points)
+    same = query_points is None
+    if exclude_ii is None:
+        exclude_ii = same
+    q = pts if same else _f32(query_points)
+    g = _complex_pairs(values, pts.shape[0])
+    f = g if query_values is None else _complex_pairs(query_values, q.shape[0])
+    s = np.zeros(2 * bins, np.float64)
+    m = np.zeros(bins, np.float64)
+    lo = np.zeros(bins, np.uint64)
+    hi = np.zeros(bins, np.uint64)
+    amb = np.zeros(1, np.uint64)
+    lib().orc_correlation(ctypes.byref(box), _p(pts), _p(g), pts.shape[0], _p(q), _p(f),
+                          q.shape[0], int(bins), float(r_min), float(r_max), int(exclude_ii),
+                          rel_band, _p(s), _p(m), _p(lo), _p(hi), _p(amb))
+    return s[0::2] + 1j * s[1::2], m, lo, hi, int(amb[0])
 
 
 def knn(box: Box, points, k: int, query_points=None, exclude_ii=None, extra: int = 1,

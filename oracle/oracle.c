@@ -1,7 +1,8 @@
 /*
  * FP64 reference oracle for periodic neighbor queries, the RDF, the 2D PMFT,
- * the 2D PMFT with relative orientation and the 3D PMFT, and a
- * Gaussian-smoothed RDF with its gradient.
+ * the 2D PMFT with relative orientation and the 3D PMFT, the spatial
+ * correlation function of per-particle values, and a Gaussian-smoothed RDF
+ * with its gradient.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
  * graded against.  Only the test suite, the smoke check and the CPU-baseline
@@ -205,6 +206,95 @@ int orc_rdf(const orc_box* b, const float* pts, int64_t n, const float* q, int64
             for (int64_t k = 0; k < bins; ++k) { lo[k] += tlo[k]; hi[k] += thi[k]; }
             amb_total += tamb;
         }
+        free(tlo);
+        free(thi);
+    }
+    *n_amb = amb_total;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Spatial correlation function of per-particle values (Analysis Modules:
+ * the density module's correlation functions of arbitrary quantities; the
+ * overview figure's correlation of the hexatic order parameter).  Values
+ * are complex (re, im as two floats); for every ball pair (i, j), query i
+ * with value f_i and point j with value g_j, r_min <= r < r_max, the term
+ * conj(f_i) g_j is added to bin b and the pair counted there; the
+ * correlation is C_b = S_b / N_b.  Terms are formed in double from the
+ * float inputs (the products are exact, the sum of two rounds once).
+ * Bin assignment and ambiguity follow the RDF: a pair within rel_band of a
+ * bin edge (in r^2) is ambiguous; it adds 1 to hi[k] and |Re term| + |Im
+ * term| to amb_mass[k] for every bin k it may reach, and nothing to
+ * sum_cert.  Certain pairs add to lo, hi and sum_cert[2b], sum_cert[2b+1].
+ * An exact implementation satisfies lo <= N <= hi and, per component,
+ * |S_b - sum_cert_b| <= amb_mass_b up to double rounding.  Pinned by:
+ * constant values (C_b = |c|^2, counts equal to the RDF's), a numpy brute
+ * force with explicit image search, a hand-computed complex pair (which
+ * side is conjugated) and the Hermitian symmetry of self-queries.
+ * ---------------------------------------------------------------------- */
+int orc_correlation(const orc_box* b, const float* pts, const float* vals, int64_t n,
+                    const float* q, const float* qvals, int64_t nq, int64_t bins, double r_min,
+                    double r_max, int32_t exclude_ii, double rel_band, double* sum_cert,
+                    double* amb_mass, uint64_t* lo, uint64_t* hi, uint64_t* n_amb)
+{
+    const double dr = (r_max - r_min) / (double)bins;
+    const double r2_lim = r_max * r_max * (1.0 + rel_band);
+    memset(sum_cert, 0, sizeof(double) * 2 * bins);
+    memset(amb_mass, 0, sizeof(double) * bins);
+    memset(lo, 0, sizeof(uint64_t) * bins);
+    memset(hi, 0, sizeof(uint64_t) * bins);
+    uint64_t amb_total = 0;
+#pragma omp parallel
+    {
+        double* ts = (double*)calloc((size_t)(2 * bins), sizeof(double));
+        double* tm = (double*)calloc((size_t)bins, sizeof(double));
+        uint64_t* tlo = (uint64_t*)calloc((size_t)bins, sizeof(uint64_t));
+        uint64_t* thi = (uint64_t*)calloc((size_t)bins, sizeof(uint64_t));
+        uint64_t tamb = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nq; ++i) {
+            const double fr = qvals[2 * i], fi = qvals[2 * i + 1];
+            double d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                if (exclude_ii && i == j) continue;
+                const double x = pair_r2(b, pts + 3 * j, q + 3 * i, d);
+                if (x >= r2_lim) continue;
+                const double gr = vals[2 * j], gi = vals[2 * j + 1];
+                /* conj(f) g = (fr - i fi)(gr + i gi) */
+                const double re = fr * gr + fi * gi;
+                const double im = fr * gi - fi * gr;
+                const int64_t blo = bin_of(x / (1.0 + rel_band), r_min, dr, bins);
+                const int64_t bhi = bin_of(x / (1.0 - rel_band), r_min, dr, bins);
+                if (blo == bhi) {
+                    if (blo >= 0 && blo < bins) {
+                        tlo[blo]++;
+                        thi[blo]++;
+                        ts[2 * blo] += re;
+                        ts[2 * blo + 1] += im;
+                    }
+                } else {
+                    ++tamb;
+                    for (int64_t k = blo; k <= bhi; ++k)
+                        if (k >= 0 && k < bins) {
+                            thi[k]++;
+                            tm[k] += fabs(re) + fabs(im);
+                        }
+                }
+            }
+        }
+#pragma omp critical
+        {
+            for (int64_t k = 0; k < bins; ++k) {
+                lo[k] += tlo[k];
+                hi[k] += thi[k];
+                amb_mass[k] += tm[k];
+                sum_cert[2 * k] += ts[2 * k];
+                sum_cert[2 * k + 1] += ts[2 * k + 1];
+            }
+            amb_total += tamb;
+        }
+        free(ts);
+        free(tm);
         free(tlo);
         free(thi);
     }
