@@ -250,6 +250,40 @@ int ppa_pmft_xyz(const ppa_box* box, const float* pts, int64_t n, const float* q
                  float x_max, float y_max, float z_max, float r_max, int32_t exclude_ii,
                  int32_t flags, void* ws, size_t ws_bytes, uint32_t* counts, hipStream_t stream);
 
+/* Workspace bytes for ppa_correlation with these arguments (nq: separate
+ * query points, 0 when the points query themselves).  Queries the current
+ * device (its compute units and LDS set the launch) but does no device
+ * work.  Same error codes as ppa_correlation's host checks. */
+int ppa_correlation_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t bins,
+                                    float r_min, float r_max, size_t* bytes);
+
+/* Spatial correlation function of per-particle values (the density
+ * module's correlation functions of arbitrary quantities, "Analysis
+ * Modules"; the paper's overview figure shows that of the hexatic order
+ * parameter).  For every ball pair (i, j), |p_j - q_i| < r_max (minimum
+ * image), excluding j == i when exclude_ii is set, with r_min <= r and bin
+ * b = floor((r - r_min) / dr), dr = (r_max - r_min) / bins:
+ *     sums[2b] + i sums[2b + 1] += conj(f_i) g_j,   counts[b] += 1,
+ * where g_j = values[j] and f_i = qvalues[i] are complex.  The correlation
+ * is C_b = (sums[2b] + i sums[2b + 1]) / counts[b] (host side).  Each term
+ * is formed in float64 from the float32 values (exact products, one
+ * rounding); bins' sums are float64, accumulated per workgroup in LDS and
+ * then summed in a fixed order.
+ *   pts [n x 3], qpts [nq x 3] or NULL, exclude_ii: as for ppa_query_ball.
+ *   values [n x 2] float32 device, 8-byte aligned: (re, im) per point (a
+ *     real quantity has im = 0).
+ *   qvalues [nq x 2] float32 device, 8-byte aligned: values of the query
+ *     points; may be NULL when qpts is NULL (the points' values are used).
+ *   bins in [1, 4096]; 0 <= r_min < r_max, r_max below half the smallest
+ *     perpendicular width.
+ *   flags: reserved, must be 0.
+ *   sums [bins x 2] float64 device, counts [bins] uint64 device: accumulated.
+ * Non-finite values set PPA_ENONFINITE in the device status. */
+int ppa_correlation(const ppa_box* box, const float* pts, const float* values, int64_t n,
+                    const float* qpts, const float* qvalues, int64_t nq, int32_t bins,
+                    float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+                    size_t ws_bytes, double* sums, uint64_t* counts, hipStream_t stream);
+
 /* Gaussian-smoothed RDF (an extension beyond the paper: a differentiable
  * form of the density module's RDF histogram).  With bins of width
  * dr = r_max / bins centred at c_b = (b + 1/2) dr and

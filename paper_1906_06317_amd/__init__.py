@@ -111,6 +111,8 @@ def lib():
             "ppa_pmft2d_workspace_bytes": [BP, i64, i64, i32, i32, f32, f32, f32,
                                            ctypes.POINTER(sz)],
             "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
+            "ppa_correlation_workspace_bytes": [BP, i64, i64, i32, f32, f32, ctypes.POINTER(sz)],
+            "ppa_correlation": [BP, P, P, i64, P, P, i64, i32, f32, f32, i32, i32, P, sz, P, P, P],
             "ppa_pmft_xyt_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32,
                                              ctypes.POINTER(sz)],
             "ppa_pmft_xyt": [BP, P, P, i64, P, P, i64, i32, i32, i32, f32, f32, f32, i32, i32, P,
@@ -546,6 +548,81 @@ def normalize_pmft_xyz(counts, n_points, n_query, volume, x_max, y_max, z_max, n
     with np.errstate(divide="ignore"):
         pmft = -np.log(pcf)
     return pcf, pmft
+
+
+def _complex_values(v, device, rows):
+    """Complex (or real) per-point values as a [rows, 2] float32 device tensor."""
+    torch = _torch()
+    if isinstance(v, torch.Tensor):
+        t = torch.view_as_real(v.to(torch.complex64)) if v.is_complex() else v
+        t = t.to(device=device, dtype=torch.float32)
+        if t.ndim == 1:
+            t = torch.stack([t, torch.zeros_like(t)], 1)
+    else:
+        a = np.asarray(v)
+        if np.iscomplexobj(a):
+            a = np.stack([a.real, a.imag], -1)
+        a = np.asarray(a, np.float32)
+        if a.ndim == 1:
+            a = np.stack([a, np.zeros_like(a)], 1)
+        t = torch.as_tensor(np.ascontiguousarray(a)).to(device)
+    t = t.contiguous().reshape(-1, 2)
+    if t.shape[0] != rows:
+        raise ValueError("one value per point is required")
+    return t
+
+
+def correlation_workspace_bytes(box: Box, n, nq, bins, r_max, r_min=0.0):
+    out = ctypes.c_size_t(0)
+    _check(lib().ppa_correlation_workspace_bytes(ctypes.byref(box.c()), int(n), int(nq), int(bins),
+                                                 float(r_min), float(r_max), ctypes.byref(out)))
+    return out.value
+
+
+def correlation_sums(box: Box, points, values, bins, r_max, r_min=0.0, query_points=None,
+                     query_values=None, exclude_ii=None, sums=None, counts=None, ws=None,
+                     stream=None, check=True):
+    """Spatial correlation sums: (sums float64 [bins, 2] = (re, im) of the sum of
+    conj(f_i) g_j per bin, counts uint64 [bins]), both accumulated.  Values are
+    complex or real per point; query values default to the points' values."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    nq = n if q is None else q.shape[0]
+    if exclude_ii is None:
+        exclude_ii = q is None
+    g = _complex_values(values, pts.device, n)
+    f = None
+    if query_values is not None:
+        f = _complex_values(query_values, pts.device, nq)
+    elif q is not None:
+        raise ValueError("query_values are required with query_points")
+    if sums is None:
+        sums = torch.zeros((int(bins), 2), dtype=torch.float64, device=pts.device)
+    if counts is None:
+        counts = torch.zeros(int(bins), dtype=torch.uint64, device=pts.device)
+    if nq == 0:
+        return sums, counts
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(correlation_workspace_bytes(box, n, 0 if q is None else nq, bins, r_max,
+                                                    r_min))
+    _check(lib().ppa_correlation(ctypes.byref(box.c()), _ptr(pts), _ptr(g), n, _ptr(q), _ptr(f),
+                                 nq, int(bins), float(r_min), float(r_max), int(bool(exclude_ii)),
+                                 0, wptr, wlen, _ptr(sums), _ptr(counts), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return sums, counts
+
+
+def correlation(box: Box, points, values, bins, r_max, r_min=0.0, **kw):
+    """C(r) per bin (complex128, host; 0 where a bin holds no pair) and the counts."""
+    sums, counts = correlation_sums(box, points, values, bins, r_max, r_min, **kw)
+    s = sums.cpu().numpy()
+    c = counts.cpu().numpy().astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        C = np.where(c > 0, (s[:, 0] + 1j * s[:, 1]) / np.maximum(c, 1), 0)
+    return C, counts
 
 
 def smooth_rdf_workspace_bytes(box: Box, n, bins, r_max, sigma):

@@ -727,6 +727,105 @@ int run_pmft3(const Pmft3Call& c, int32_t exclude_ii, int32_t flags, void* ws, s
 }
 
 // ---------------------------------------------------------------------------
+// Spatial correlation function: plan, workspace and launches.
+// ---------------------------------------------------------------------------
+struct CorrPlan {
+    Grid g;
+    int blocks;
+};
+
+int corr_plan(const BoxPrep& bp, int64_t n, int32_t bins, float r_min, float r_max, CorrPlan* P)
+{
+    if (bins < 1 || bins > kCorrMaxBins)
+        return set_error(PPA_EINVAL, "bins must be in [1, %d]", kCorrMaxBins);
+    if (!(isfinite(r_min) && isfinite(r_max) && r_min >= 0.f && r_min < r_max))
+        return set_error(PPA_EINVAL, "need 0 <= r_min < r_max");
+    int rc;
+    if ((rc = check_cutoff(bp, r_max))) return rc;
+    pair_grid(bp, r_max, n, &P->g);
+    P->blocks = corr_workgroups(bp.dim, bins, P->g.ncells);
+    return PPA_OK;
+}
+
+size_t corr_layout(const CorrPlan& P, int64_t n, int64_t nq_sep, int32_t bins, void* base_v,
+                   Workspace* W, CorrArgs* A)
+{
+    char* base = (char*)base_v;
+    size_t off = workspace_layout(P.g, n, nq_sep, 0, base_v, W);
+    const size_t rows = (size_t)partial_rows(P.blocks);
+    auto take = [&](size_t bytes) {
+        void* p = base ? (void*)(base + off) : nullptr;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    A->psum = (double*)take(sizeof(double) * 2 * (size_t)bins * P.blocks);
+    A->pcnt = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)bins * P.blocks);
+    A->lsum = (double*)take(sizeof(double) * 2 * (size_t)bins * rows);
+    A->lcnt = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)bins * rows);
+    return off;
+}
+
+int run_corr(const ppa_box* box, const float* pts, const float* values, int64_t n,
+             const float* qpts, const float* qvalues, int64_t nq, int32_t bins, float r_min,
+             float r_max, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
+             double* sums, uint64_t* counts, hipStream_t s)
+{
+    if (!pts && n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    if (n > 0x7fffffffLL || nq > 0x7fffffffLL)
+        return set_error(PPA_EINVAL, "point counts are limited to 2^31 - 1");
+    if (!qpts && nq != n) return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (!values && n > 0) return set_error(PPA_EINVAL, "values pointer is NULL");
+    if (qpts && !qvalues && nq > 0) return set_error(PPA_EINVAL, "query values pointer is NULL");
+    if (((uintptr_t)values & 7) || ((uintptr_t)qvalues & 7))
+        return set_error(PPA_EINVAL, "values must be 8-byte aligned");
+    if (!sums || !counts) return set_error(PPA_EINVAL, "output pointer is NULL");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    CorrPlan P;
+    if ((rc = corr_plan(bp, n, bins, r_min, r_max, &P))) return rc;
+    const int64_t nq_sep = qpts ? nq : 0;
+    Workspace W{};
+    CorrArgs A{};
+    const size_t need = corr_layout(P, n, nq_sep, bins, nullptr, &W, &A);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    corr_layout(P, n, nq_sep, bins, ws, &W, &A);
+    if (nq == 0) return PPA_OK;
+    const Grid& g = P.g;
+    launch_zero(W, g, qpts != nullptr, nullptr, 0, s);
+    launch_build_cells(pts, W.pts, bp, g, W.status, s);
+    if (qpts) launch_build_cells(qpts, W.qry, bp, g, W.status, s);
+
+    A.cand = W.pts.local;
+    A.cand_start = W.pts.cell_start;
+    A.qsorted = W.qry.local;
+    A.q_start = W.qry.cell_start;
+    A.pval = (const float2*)values;
+    A.qval = (const float2*)(qvalues ? qvalues : values);
+    for (int d = 0; d < 3; ++d) A.geom.n[d] = g.n[d];
+    A.geom.ncells = g.ncells;
+    A.geom.nsten = g.nsten;
+    memcpy(A.geom.off, g.off, sizeof(A.geom.off));
+    A.geom.r2max = r_max * r_max;
+    A.excl = exclude_ii ? 1 : 0;
+    A.bins = bins;
+    A.r_min = r_min;
+    A.inv_dr = (float)((double)bins / ((double)r_max - (double)r_min));
+    A.sums = sums;
+    A.counts = (unsigned long long*)counts;
+    A.status = W.status;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], s);
+    launch_corr(A, bp.dim, P.blocks, s);
+    record(pe.ev[3], s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+// ---------------------------------------------------------------------------
 // Gaussian-smoothed RDF: plan, workspace and launches.
 // ---------------------------------------------------------------------------
 struct SmoothPlan {
@@ -979,6 +1078,31 @@ int ppa_pmft2d(const ppa_box* box, const float* pts, int64_t n, const float* qpt
 {
     return run_pmft(box, pts, n, qpts, angles, nq, nbx, nby, x_max, y_max, r_max, exclude_ii,
                     flags, ws, ws_bytes, counts, stream);
+}
+
+int ppa_correlation_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t bins,
+                                    float r_min, float r_max, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0 || nq < 0) return set_error(PPA_EINVAL, "negative point count");
+    BoxPrep bp;
+    int rc = prepare_box(box, &bp);
+    if (rc) return rc;
+    CorrPlan P;
+    if ((rc = corr_plan(bp, n, bins, r_min, r_max, &P))) return rc;
+    Workspace W{};
+    CorrArgs A{};
+    *bytes = corr_layout(P, n, nq, bins, nullptr, &W, &A);
+    return PPA_OK;
+}
+
+int ppa_correlation(const ppa_box* box, const float* pts, const float* values, int64_t n,
+                    const float* qpts, const float* qvalues, int64_t nq, int32_t bins,
+                    float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
+                    size_t ws_bytes, double* sums, uint64_t* counts, hipStream_t stream)
+{
+    return run_corr(box, pts, values, n, qpts, qvalues, nq, bins, r_min, r_max, exclude_ii, flags,
+                    ws, ws_bytes, sums, counts, stream);
 }
 
 int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,

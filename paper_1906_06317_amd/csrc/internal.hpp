@@ -254,6 +254,34 @@ struct Pmft3Args {
 
 void launch_pmft3(const Pmft3Args& a, hipStream_t s);
 
+// Spatial correlation function of per-particle values (corr.hip).
+constexpr int kCorrMaxBins = 4096;
+
+struct CorrArgs {
+    const float4* cand;       // points sorted by cell
+    const int* cand_start;    // [ncells + 1]
+    const float4* qsorted;    // query points sorted by cell
+    const int* q_start;       // [ncells + 1]
+    const float2* pval;       // [n] complex value of each point
+    const float2* qval;       // [nq] complex value of each query point
+    PairGeom geom;
+    int excl;                 // 1: drop the point whose index is the query's
+    int bins;
+    float r_min;
+    float inv_dr;             // bins / (r_max - r_min)
+    double* psum;             // [blocks][2 bins] per-workgroup sums (re, im)
+    unsigned long long* pcnt; // [blocks][bins] per-workgroup counts
+    double* lsum;             // [rows][2 bins] first-stage sums
+    unsigned long long* lcnt; // [rows][bins]
+    double* sums;             // [bins][2] accumulated
+    unsigned long long* counts;  // [bins] accumulated
+    unsigned* status;
+};
+
+size_t corr_lds_bytes(int bins);
+int corr_workgroups(int dim, int bins, long long ncells);
+void launch_corr(const CorrArgs& a, int dim, int blocks, hipStream_t s);
+
 // Gaussian-smoothed RDF and its adjoint (smooth.hip).
 constexpr int kSmoothMaxBins = 4096;
 
