@@ -463,6 +463,42 @@ def row_pmft(ppa, hip):
             "pairs_per_s": pairs / (ms * 1e-3)}
 
 
+def row_correlation(ppa, hip):
+    """Spatial correlation of psi_6-like values on the 2D fluid."""
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s = workloads.fluid_2d()
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    psi = np.exp(6j * s.theta.astype(np.float64)).astype(np.complex64)
+    vals = torch.as_tensor(np.stack([psi.real, psi.imag], 1)).cuda()
+    bins, r_max = 120, 6.0
+    sums = torch.zeros((bins, 2), dtype=torch.float64, device="cuda")
+    counts = torch.zeros(bins, dtype=torch.uint64, device="cuda")
+    evs = []
+
+    def call():
+        e = hip.events(2)
+        evs.append(e)
+        L.ppa_profile_next(None, None, e[0], e[1])
+        ppa.correlation_sums(box, pts, vals, bins, r_max, sums=sums, counts=counts, check=False)
+    ms = timed(call, 10, warmup=2)
+    kern = float(np.mean([hip.ms(e[0], e[1]) for e in evs[2:]]))
+    for e in evs:
+        hip.destroy(e)
+    if ppa.default_workspace().status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+    pairs = int(counts.cpu().numpy().astype(np.int64).sum()) // 12
+    return {"workload": "2D fluid N=262,144, density 0.7, values exp(6i theta) (theta uniform), "
+                        "r_max=6, 120 bins; sums of conj(f_i) g_j in float64",
+            "ms": ms, "kernels_ms": kern, "pairs": pairs, "pairs_per_s": pairs / (ms * 1e-3),
+            "lds_atomics_per_pair": 3,
+            "lds_atomics_per_s": 3 * pairs / (kern * 1e-3)}
+
+
 def row_batched(ppa, hip):
     import numpy as np
     import torch
@@ -618,6 +654,9 @@ def main():
         gpeak = global_atomic_peak(ppa)
         rows["global_atomic_probe"] = gpeak
         rows["pmft3"] = row_pmft3(ppa, hip, gpeak)
+        rows["correlation"] = row_correlation(ppa, hip)
+        rows["correlation"]["frac_of_lds_atomic_probe"] = (
+            rows["correlation"]["lds_atomics_per_s"] / peak["256_bins_per_s"])
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
         rows["paper_context"] = paper_context(ppa)

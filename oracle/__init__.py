@@ -12,8 +12,9 @@ helpers below (RDF, PMF, PMFT, smoothed RDF) are closed-form FP64 numpy.
 Each function names the part of the paper it follows.  Parity status:
   * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts, the 2D
     PMFT with relative orientation (XYT) and the 3D PMFT (XYZ) counts, the
-    spatial correlation function, smoothed RDF and its gradient: pinned
-    (see tests/test_oracle_*.py);
+    spatial correlation function, Steinhardt Q_l and W_l with the Wigner
+    3j symbols, smoothed RDF and its gradient: pinned (see
+    tests/test_oracle_*.py);
   * RDF / PMFT normalisation constants: the paper defines the PMF and PMFT
     only up to an additive constant, so the convention below is a reading,
     pinned statistically by the ideal-gas limit only.
@@ -321,6 +322,82 @@ def smooth_rdf_grad(box: Box, points, bins: int, r_max: float, sigma: float, gra
 # the accumulated histogram; it states no normalisation, so these follow the
 # usual ideal-gas one.
 # ---------------------------------------------------------------------------
+
+def wigner3j(j1: int, j2: int, j3: int, m1: int, m2: int, m3: int) -> float:
+    """Wigner 3j symbol by the Racah formula, in exact rational arithmetic
+    (integer j and m only)."""
+    from fractions import Fraction
+    from math import factorial as F, isqrt
+    if m1 + m2 + m3 != 0 or abs(m1) > j1 or abs(m2) > j2 or abs(m3) > j3:
+        return 0.0
+    if j3 < abs(j1 - j2) or j3 > j1 + j2:
+        return 0.0
+    tri = Fraction(F(j1 + j2 - j3) * F(j1 - j2 + j3) * F(-j1 + j2 + j3), F(j1 + j2 + j3 + 1))
+    pre = tri * F(j1 + m1) * F(j1 - m1) * F(j2 + m2) * F(j2 - m2) * F(j3 + m3) * F(j3 - m3)
+    total = Fraction(0)
+    for k in range(0, j1 + j2 + j3 + 1):
+        args = (k, j3 - j2 + k + m1, j3 - j1 + k - m2, j1 + j2 - j3 - k, j1 - k - m1, j2 - k + m2)
+        if min(args) < 0:
+            continue
+        den = 1
+        for a in args:
+            den *= F(a)
+        total += Fraction((-1) ** k, den)
+    sign = -1.0 if (j1 - j2 - m3) % 2 else 1.0
+    return sign * math.sqrt(float(pre)) * float(total)
+
+
+def steinhardt(box: Box, points, offsets, point_idx, l: int, query_points=None):
+    """Steinhardt order parameters of each query row of a NeighborList (the
+    paper's order-parameter features and its Q6 example on 12-neighbour
+    lists; definitions after Steinhardt, Nelson and Ronchetti): with bonds
+    d = minimum image of p_j - q_i (bonds of length 0 skipped) and Y_lm from
+    scipy,
+        q_lm(i) = mean over bonds of Y_lm(d),
+        Q_l(i) = sqrt(4 pi / (2l + 1) * sum_m |q_lm|^2),
+        W_l(i) = sum_{m1+m2+m3=0} (l l l; m1 m2 m3) q_lm1 q_lm2 q_lm3
+                 / (sum_m |q_lm|^2)^(3/2)   (the normalised W-hat).
+    Rows without bonds give 0.  Returns (Q_l, W_l) float64 [nq]."""
+    from scipy.special import sph_harm_y
+    pts = np.asarray(points, np.float32).astype(np.float64)
+    q = pts if query_points is None else np.asarray(query_points, np.float32).astype(np.float64)
+    off = np.asarray(offsets, np.int64)
+    idx = np.asarray(point_idx, np.int64)[: off[-1]]
+    nq = off.shape[0] - 1
+    rows = np.repeat(np.arange(nq), np.diff(off))
+    d = pts[idx] - q[rows]
+    if box.dim == 2:
+        d[:, 2] = 0.0
+    d = np.ascontiguousarray(d)
+    lib().orc_minimum_image(ctypes.byref(box), _p(d), d.shape[0])
+    r = np.sqrt((d ** 2).sum(1))
+    keep = r > 0
+    rows, d, r = rows[keep], d[keep], r[keep]
+    theta = np.arccos(np.clip(d[:, 2] / r, -1.0, 1.0))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    nb = np.bincount(rows, minlength=nq).astype(np.float64)
+    qlm = np.zeros((nq, 2 * l + 1), np.complex128)
+    for m in range(-l, l + 1):
+        Y = sph_harm_y(l, m, theta, phi)
+        qlm[:, m + l] = np.bincount(rows, weights=Y.real, minlength=nq) + \
+            1j * np.bincount(rows, weights=Y.imag, minlength=nq)
+    has = nb > 0
+    qlm[has] /= nb[has, None]
+    s2 = (np.abs(qlm) ** 2).sum(1)
+    Q = np.sqrt(4 * math.pi / (2 * l + 1) * s2)
+    W = np.zeros(nq, np.complex128)
+    for m1 in range(-l, l + 1):
+        for m2 in range(-l, l + 1):
+            m3 = -m1 - m2
+            if abs(m3) > l:
+                continue
+            w = wigner3j(l, l, l, m1, m2, m3)
+            if w != 0.0:
+                W += w * qlm[:, m1 + l] * qlm[:, m2 + l] * qlm[:, m3 + l]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Wh = np.where(s2 > 0, W.real / np.maximum(s2, 1e-300) ** 1.5, 0.0)
+    return np.where(has, Q, 0.0), np.where(has, Wh, 0.0)
+
 
 def box_volume(L, dim=3):
     L = np.broadcast_to(np.asarray(L, np.float64), (3,))
