@@ -284,6 +284,36 @@ int ppa_correlation(const ppa_box* box, const float* pts, const float* values, i
                     float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
                     size_t ws_bytes, double* sums, uint64_t* counts, hipStream_t stream);
 
+/* Workspace bytes for ppa_steinhardt with degree l (host only). */
+int ppa_steinhardt_workspace_bytes(int32_t l, int32_t flags, size_t* bytes);
+
+/* Steinhardt bond-orientational order parameters of the rows of a
+ * NeighborList (the paper's order-parameter features; its example computes
+ * Q6 on the 12-nearest-neighbour list, definitions after Steinhardt, Nelson
+ * and Ronchetti).  For query i with bonds d_ij = p_j - q_i over its row
+ * (minimum image; bonds of length 0 are skipped, N_b counts the others):
+ *     q_lm(i) = (1 / N_b) sum_j Y_lm(d_ij),
+ *     ql[i] = Q_l(i) = sqrt(4 pi / (2l + 1) sum_m |q_lm|^2),
+ *     wl[i] = sum_{m1+m2+m3=0} (l l l; m1 m2 m3) q_lm1 q_lm2 q_lm3
+ *             / (sum_m |q_lm|^2)^(3/2)      (the normalised W-hat),
+ * with Y_lm the orthonormal spherical harmonics (polar angle from +z).
+ * Rows without bonds give 0.  Computed in float64.
+ *   pts [n x 3], qpts [nq x 3] or NULL (the points are the queries):
+ *     float32 device, the positions the list was built from.
+ *   offsets [nq + 1] int64 device, point_idx [capacity] int32 device: the
+ *     NeighborList (any CSR list, e.g. from ppa_query_knn or
+ *     ppa_query_ball).  An offset outside [0, capacity], decreasing offsets
+ *     or an index outside [0, n) is skipped and sets the device status to
+ *     PPA_EINVAL.  Bonds are taken as the image in the centred box cell, the
+ *     minimum image for every bond shorter than half the smallest width.
+ *   l in [0, 12]; flags: reserved, must be 0.
+ *   ws: ppa_steinhardt_workspace_bytes(l) bytes (status and 3j table).
+ *   ql [nq] float64 device; wl [nq] float64 device or NULL (Q_l only). */
+int ppa_steinhardt(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   const int64_t* offsets, const int32_t* point_idx, int64_t capacity, int32_t l,
+                   int32_t flags, void* ws, size_t ws_bytes, double* ql, double* wl,
+                   hipStream_t stream);
+
 /* Gaussian-smoothed RDF (an extension beyond the paper: a differentiable
  * form of the density module's RDF histogram).  With bins of width
  * dr = r_max / bins centred at c_b = (b + 1/2) dr and

@@ -113,6 +113,8 @@ def lib():
             "ppa_pmft2d": [BP, P, i64, P, P, i64, i32, i32, f32, f32, f32, i32, i32, P, sz, P, P],
             "ppa_correlation_workspace_bytes": [BP, i64, i64, i32, f32, f32, ctypes.POINTER(sz)],
             "ppa_correlation": [BP, P, P, i64, P, P, i64, i32, f32, f32, i32, i32, P, sz, P, P, P],
+            "ppa_steinhardt_workspace_bytes": [i32, i32, ctypes.POINTER(sz)],
+            "ppa_steinhardt": [BP, P, i64, P, i64, P, P, i64, i32, i32, P, sz, P, P, P],
             "ppa_pmft_xyt_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32,
                                              ctypes.POINTER(sz)],
             "ppa_pmft_xyt": [BP, P, P, i64, P, P, i64, i32, i32, i32, f32, f32, f32, i32, i32, P,
@@ -623,6 +625,46 @@ def correlation(box: Box, points, values, bins, r_max, r_min=0.0, **kw):
     with np.errstate(invalid="ignore", divide="ignore"):
         C = np.where(c > 0, (s[:, 0] + 1j * s[:, 1]) / np.maximum(c, 1), 0)
     return C, counts
+
+
+def steinhardt(box: Box, points, neighbors, l, query_points=None, with_w=False, ws=None,
+               stream=None, check=True):
+    """Steinhardt Q_l (and normalised W_l with with_w) of every query row of a
+    NeighborList, float64 [nq] device tensors: (ql, wl or None).
+
+    `neighbors` is a NeighborList (offsets, point_idx) built on these
+    positions, or a tuple (offsets, point_idx) of device or host arrays."""
+    torch = _torch()
+    pts = _points(points)
+    n = pts.shape[0]
+    q = None if query_points is None else _points(query_points)
+    if isinstance(neighbors, NeighborList):
+        off, idx = neighbors.offsets, neighbors.point_idx
+    else:
+        off, idx = neighbors
+    off = torch.as_tensor(np.asarray(off) if not isinstance(off, torch.Tensor) else off)
+    idx = torch.as_tensor(np.asarray(idx) if not isinstance(idx, torch.Tensor) else idx)
+    off = off.to(device=pts.device, dtype=torch.int64).contiguous()
+    idx = idx.to(device=pts.device, dtype=torch.int32).contiguous()
+    nq = off.shape[0] - 1
+    if q is None and nq != n:
+        raise ValueError("a list over the points needs n + 1 offsets")
+    if q is not None and q.shape[0] != nq:
+        raise ValueError("one offset row per query point is required")
+    ql = torch.zeros(max(nq, 0), dtype=torch.float64, device=pts.device)
+    wl = torch.zeros(max(nq, 0), dtype=torch.float64, device=pts.device) if with_w else None
+    if nq == 0:
+        return ql, wl
+    need = ctypes.c_size_t(0)
+    _check(lib().ppa_steinhardt_workspace_bytes(int(l), 0, ctypes.byref(need)))
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(need.value)
+    _check(lib().ppa_steinhardt(ctypes.byref(box.c()), _ptr(pts), n, _ptr(q), nq, _ptr(off),
+                                _ptr(idx) if idx.numel() else None, idx.numel(), int(l), 0, wptr,
+                                wlen, _ptr(ql), _ptr(wl), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    return ql, wl
 
 
 def smooth_rdf_workspace_bytes(box: Box, n, bins, r_max, sigma):

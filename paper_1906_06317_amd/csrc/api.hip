@@ -1105,6 +1105,61 @@ int ppa_correlation(const ppa_box* box, const float* pts, const float* values, i
                     ws, ws_bytes, sums, counts, stream);
 }
 
+int ppa_steinhardt_workspace_bytes(int32_t l, int32_t flags, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (l < 0 || l > kSteinMaxL) return set_error(PPA_EINVAL, "l must be in [0, %d]", kSteinMaxL);
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    const size_t w = 2 * (size_t)l + 1;
+    *bytes = 256 + ((sizeof(double) * w * w + 255) & ~(size_t)255);
+    return PPA_OK;
+}
+
+int ppa_steinhardt(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   const int64_t* offsets, const int32_t* point_idx, int64_t capacity, int32_t l,
+                   int32_t flags, void* ws, size_t ws_bytes, double* ql, double* wl,
+                   hipStream_t stream)
+{
+    if (n < 0 || nq < 0 || capacity < 0) return set_error(PPA_EINVAL, "negative size");
+    if (!pts && n > 0) return set_error(PPA_EINVAL, "points pointer is NULL");
+    if (!qpts && nq != n) return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
+    if (!offsets) return set_error(PPA_EINVAL, "offsets pointer is NULL");
+    if (!point_idx && capacity > 0) return set_error(PPA_EINVAL, "point_idx pointer is NULL");
+    if (!ql && nq > 0) return set_error(PPA_EINVAL, "output pointer is NULL");
+    size_t need = 0;
+    int rc = ppa_steinhardt_workspace_bytes(l, flags, &need);
+    if (rc) return rc;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    BoxPrep bp;
+    if ((rc = prepare_box(box, &bp))) return rc;
+    unsigned* status = (unsigned*)ws;
+    double* table = (double*)((char*)ws + 256);
+    launch_steinhardt_setup(l, wl != nullptr, table, status, stream);
+    SteinArgs A{};
+    A.pts = pts;
+    A.qpts = qpts ? qpts : pts;
+    A.offsets = offsets;
+    A.idx = point_idx;
+    A.n = n;
+    A.nq = nq;
+    A.capacity = capacity;
+    A.l = l;
+    A.dim = bp.dim;
+    memcpy(A.m, bp.M, sizeof(A.m));
+    memcpy(A.minv, bp.Minv, sizeof(A.minv));
+    A.w3j = wl ? table : nullptr;
+    A.ql = ql;
+    A.wl = wl;
+    A.status = status;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], stream);
+    launch_steinhardt(A, stream);
+    record(pe.ev[3], stream);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
                                  int32_t nby, int32_t nbt, float x_max, float y_max, float r_max,
                                  size_t* bytes)
@@ -1190,6 +1245,8 @@ int ppa_sync_status(const void* ws, hipStream_t stream)
     if (rc) return rc;
     if (st & kStatusNonFinite) return set_error(PPA_ENONFINITE, "input has a non-finite coordinate");
     if (st & kStatusCapacity) return set_error(PPA_ECAPACITY, "more pairs than the output capacity");
+    if (st & kStatusBadList)
+        return set_error(PPA_EINVAL, "a NeighborList offset or point index is out of range");
     if (st & kStatusRange)
         return set_error(PPA_ERANGE,
                          "a k-nearest row needs a neighbour at or beyond half the smallest "

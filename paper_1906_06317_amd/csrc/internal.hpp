@@ -19,6 +19,7 @@ constexpr int kMaxLdsBins = 4096;       // histograms up to this size live in LD
 constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusCapacity = 2u;
 constexpr unsigned kStatusRange = 4u;   // a k-nearest row reaches half the box width
+constexpr unsigned kStatusBadList = 8u; // a NeighborList offset or index out of range
 
 // Box prepared on the host in float64.
 struct BoxPrep {
@@ -281,6 +282,28 @@ struct CorrArgs {
 size_t corr_lds_bytes(int bins);
 int corr_workgroups(int dim, int bins, long long ncells);
 void launch_corr(const CorrArgs& a, int dim, int blocks, hipStream_t s);
+
+// Steinhardt order parameters of NeighborList rows (steinhardt.hip).
+constexpr int kSteinMaxL = 12;
+
+struct SteinArgs {
+    const float* pts;         // [n][3]
+    const float* qpts;        // [nq][3] (pts when the points query themselves)
+    const int64_t* offsets;   // [nq + 1]
+    const int32_t* idx;       // [capacity]
+    long long n, nq, capacity;
+    int l;
+    int dim;
+    double m[3][3];           // box matrix (columns a1, a2, a3)
+    double minv[3][3];
+    const double* w3j;        // [(2l+1)^2] (l l l; m1 m2 -m1-m2), or NULL without W
+    double* ql;               // [nq]
+    double* wl;               // [nq] or NULL
+    unsigned* status;
+};
+
+void launch_steinhardt_setup(int l, bool want_w, double* table, unsigned* status, hipStream_t s);
+void launch_steinhardt(const SteinArgs& a, hipStream_t s);
 
 // Gaussian-smoothed RDF and its adjoint (smooth.hip).
 constexpr int kSmoothMaxBins = 4096;
