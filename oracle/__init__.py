@@ -13,7 +13,7 @@ Each function names the part of the paper it follows.  Parity status:
   * minimum image, ball query, RDF counts, k-NN, 2D PMFT counts, the 2D
     PMFT with relative orientation (XYT) and the 3D PMFT (XYZ) counts, the
     spatial correlation function, Steinhardt Q_l and W_l with the Wigner
-    3j symbols, smoothed RDF and its gradient: pinned (see
+    3j symbols, clusters, smoothed RDF and its gradient: pinned (see
     tests/test_oracle_*.py);
   * RDF / PMFT normalisation constants: the paper defines the PMF and PMFT
     only up to an additive constant, so the convention below is a reading,
@@ -397,6 +397,31 @@ def steinhardt(box: Box, points, offsets, point_idx, l: int, query_points=None):
     with np.errstate(invalid="ignore", divide="ignore"):
         Wh = np.where(s2 > 0, W.real / np.maximum(s2, 1e-300) ** 1.5, 0.0)
     return np.where(has, Q, 0.0), np.where(has, Wh, 0.0)
+
+
+def clusters(n: int, offsets, point_idx):
+    """Clusters of the cluster module (Analysis Modules: membership defined by
+    neighbour bonds): connected components of the undirected graph on n
+    points whose edges are the pairs (i, point_idx[e]) of every row i of the
+    list.  Returns (labels, cluster_idx, sizes): labels[i] = smallest point
+    index of i's component; cluster_idx[i] numbers the components in order
+    of their smallest index; sizes[c] = points in component c."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    off = np.asarray(offsets, np.int64)
+    idx = np.asarray(point_idx, np.int64)[: off[-1]]
+    rows = np.repeat(np.arange(off.shape[0] - 1), np.diff(off))
+    g = csr_matrix((np.ones(idx.shape[0]), (rows, idx)), shape=(n, n))
+    nc, comp = connected_components(g, directed=True, connection="weak")
+    first = np.full(nc, n, np.int64)
+    np.minimum.at(first, comp, np.arange(n))
+    labels = first[comp]
+    order = np.argsort(first)               # components by smallest member
+    rank = np.empty(nc, np.int64)
+    rank[order] = np.arange(nc)
+    cidx = rank[comp]
+    sizes = np.bincount(cidx, minlength=nc)
+    return labels.astype(np.int64), cidx.astype(np.int64), sizes.astype(np.int64)
 
 
 def box_volume(L, dim=3):
