@@ -314,6 +314,33 @@ int ppa_steinhardt(const ppa_box* box, const float* pts, int64_t n, const float*
                    int32_t flags, void* ws, size_t ws_bytes, double* ql, double* wl,
                    hipStream_t stream);
 
+/* Workspace bytes for ppa_cluster on n points (host only). */
+int ppa_cluster_workspace_bytes(int64_t n, size_t* bytes);
+
+/* Clusters (the cluster module, "Analysis Modules": membership defined by
+ * neighbour bonds): the connected components of the undirected graph on the
+ * n points whose edges are the pairs (i, point_idx[e]) of every row i of a
+ * NeighborList over these points (a bond listed in one direction only, as
+ * in a k-nearest list, still joins both points).
+ *   offsets [n + 1] int64 device, point_idx [capacity] int32 device: the
+ *     list, row i belonging to point i (e.g. ppa_query_ball of the points
+ *     with themselves).  An offset outside [0, capacity], decreasing
+ *     offsets or an index outside [0, n) is skipped and sets the device
+ *     status to PPA_EINVAL.
+ *   flags: reserved, must be 0.
+ *   labels [n] int32 device: the smallest point index of each point's
+ *     component (deterministic, independent of scheduling).
+ *   cluster_idx [n] int32 device or NULL: components numbered 0, 1, ... in
+ *     order of their smallest point index.
+ *   sizes [n] int32 device or NULL: sizes[c] = points of component c for
+ *     c < number of components (the rest 0).
+ *   n_clusters_dev int64 device or NULL: the number of components.
+ * Lock-free union-find on the device (compare-and-swap linking of the
+ * larger root under the smaller, path halving); no host synchronisation. */
+int ppa_cluster(const int64_t* offsets, const int32_t* point_idx, int64_t n, int64_t capacity,
+                int32_t flags, void* ws, size_t ws_bytes, int32_t* labels, int32_t* cluster_idx,
+                int32_t* sizes, int64_t* n_clusters_dev, hipStream_t stream);
+
 /* Gaussian-smoothed RDF (an extension beyond the paper: a differentiable
  * form of the density module's RDF histogram).  With bins of width
  * dr = r_max / bins centred at c_b = (b + 1/2) dr and

@@ -115,6 +115,8 @@ def lib():
             "ppa_correlation": [BP, P, P, i64, P, P, i64, i32, f32, f32, i32, i32, P, sz, P, P, P],
             "ppa_steinhardt_workspace_bytes": [i32, i32, ctypes.POINTER(sz)],
             "ppa_steinhardt": [BP, P, i64, P, i64, P, P, i64, i32, i32, P, sz, P, P, P],
+            "ppa_cluster_workspace_bytes": [i64, ctypes.POINTER(sz)],
+            "ppa_cluster": [P, P, i64, i64, i32, P, sz, P, P, P, P, P],
             "ppa_pmft_xyt_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32,
                                              ctypes.POINTER(sz)],
             "ppa_pmft_xyt": [BP, P, P, i64, P, P, i64, i32, i32, i32, f32, f32, f32, i32, i32, P,
@@ -665,6 +667,41 @@ def steinhardt(box: Box, points, neighbors, l, query_points=None, with_w=False, 
     if check:
         _check(ws.status(stream))
     return ql, wl
+
+
+def clusters(neighbors, n, ws=None, stream=None, check=True):
+    """Connected components of a NeighborList over n points (bonds as
+    undirected edges): (labels, cluster_idx, sizes, n_clusters) with labels
+    the smallest index of each point's component, cluster_idx the components
+    numbered by that index, sizes[:n_clusters] their point counts."""
+    torch = _torch()
+    if isinstance(neighbors, NeighborList):
+        off, idx = neighbors.offsets, neighbors.point_idx
+    else:
+        off, idx = neighbors
+    dev = "cuda"
+    off = torch.as_tensor(np.asarray(off) if not isinstance(off, torch.Tensor) else off)
+    idx = torch.as_tensor(np.asarray(idx) if not isinstance(idx, torch.Tensor) else idx)
+    off = off.to(device=dev, dtype=torch.int64).contiguous()
+    idx = idx.to(device=dev, dtype=torch.int32).contiguous()
+    n = int(n)
+    if off.shape[0] != n + 1:
+        raise ValueError("the list needs n + 1 offsets (row i is point i)")
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    cidx = torch.empty(n, dtype=torch.int32, device=dev)
+    sizes = torch.empty(n, dtype=torch.int32, device=dev)
+    nc = torch.zeros(1, dtype=torch.int64, device=dev)
+    need = ctypes.c_size_t(0)
+    _check(lib().ppa_cluster_workspace_bytes(n, ctypes.byref(need)))
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(need.value)
+    _check(lib().ppa_cluster(_ptr(off), _ptr(idx) if idx.numel() else None, n, idx.numel(), 0,
+                             wptr, wlen, _ptr(labels) if n else None, _ptr(cidx) if n else None,
+                             _ptr(sizes) if n else None, _ptr(nc), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    k = int(nc.item())
+    return labels, cidx, sizes[:k], k
 
 
 def smooth_rdf_workspace_bytes(box: Box, n, bins, r_max, sigma):

@@ -1160,6 +1160,65 @@ int ppa_steinhardt(const ppa_box* box, const float* pts, int64_t n, const float*
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+static size_t cluster_layout(int64_t n, void* base_v, ClusterArgs* A)
+{
+    char* base = (char*)base_v;
+    size_t off = 256;  // header: status word at 0, scan ticket at 64, round flags at 128
+    const size_t flag_bytes = sizeof(unsigned long long) * scan_flag_count(n) + 256;
+    A->status = (unsigned*)base;
+    A->ticket = base ? (int*)(base + 64) : nullptr;
+    A->round_flags = base ? (int*)(base + 128) : nullptr;  // kClusterRounds ints
+    static_assert(128 + 4 * kClusterRounds <= 256, "round flags exceed the header");
+    A->scan_flags = base ? (unsigned long long*)(base + off) : nullptr;
+    off = (off + flag_bytes + 255) & ~(size_t)255;
+    A->zero = (unsigned*)base;
+    A->zero_bytes = off;
+    A->is_root = base ? (int*)(base + off) : nullptr;
+    off = (off + sizeof(int) * (size_t)n + 255) & ~(size_t)255;
+    A->rank = base ? (int64_t*)(base + off) : nullptr;
+    off = (off + sizeof(int64_t) * (size_t)(n + 1) + 255) & ~(size_t)255;
+    return off;
+}
+
+int ppa_cluster_workspace_bytes(int64_t n, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (n < 0 || n > 0x7fffffffLL) return set_error(PPA_EINVAL, "bad point count");
+    ClusterArgs A{};
+    *bytes = cluster_layout(n, nullptr, &A);
+    return PPA_OK;
+}
+
+int ppa_cluster(const int64_t* offsets, const int32_t* point_idx, int64_t n, int64_t capacity,
+                int32_t flags, void* ws, size_t ws_bytes, int32_t* labels, int32_t* cluster_idx,
+                int32_t* sizes, int64_t* n_clusters_dev, hipStream_t stream)
+{
+    if (n < 0 || n > 0x7fffffffLL || capacity < 0) return set_error(PPA_EINVAL, "bad size");
+    if (!offsets) return set_error(PPA_EINVAL, "offsets pointer is NULL");
+    if (!point_idx && capacity > 0) return set_error(PPA_EINVAL, "point_idx pointer is NULL");
+    if (!labels && n > 0) return set_error(PPA_EINVAL, "labels pointer is NULL");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    ClusterArgs A{};
+    const size_t need = cluster_layout(n, nullptr, &A);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    cluster_layout(n, ws, &A);
+    A.offsets = offsets;
+    A.idx = point_idx;
+    A.n = n;
+    A.capacity = capacity;
+    A.labels = labels;
+    A.cluster_idx = cluster_idx;
+    A.sizes = sizes;
+    A.n_clusters = n_clusters_dev;
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], stream);
+    launch_cluster(A, stream);
+    record(pe.ev[3], stream);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
                                  int32_t nby, int32_t nbt, float x_max, float y_max, float r_max,
                                  size_t* bytes)

@@ -305,6 +305,29 @@ struct SteinArgs {
 void launch_steinhardt_setup(int l, bool want_w, double* table, unsigned* status, hipStream_t s);
 void launch_steinhardt(const SteinArgs& a, hipStream_t s);
 
+// Clusters: connected components of NeighborList bonds (cluster.hip).
+constexpr int kClusterRounds = 12;  // hooking rounds at most (flags in the header)
+
+struct ClusterArgs {
+    const int64_t* offsets;   // [n + 1]
+    const int32_t* idx;       // [capacity]
+    long long n, capacity;
+    int* labels;              // [n] out: smallest index of the component
+    int32_t* cluster_idx;     // [n] or NULL
+    int32_t* sizes;           // [n] or NULL (first n_clusters entries used)
+    int64_t* n_clusters;      // device or NULL
+    unsigned* status;         // workspace header
+    int* ticket;              // scan tile ticket (workspace header)
+    int* round_flags;         // [kClusterRounds] changes per hooking round (header)
+    unsigned long long* scan_flags;
+    int* is_root;             // [n]
+    int64_t* rank;            // [n + 1]
+    unsigned* zero;           // start of the region cleared per call
+    size_t zero_bytes;
+};
+
+void launch_cluster(const ClusterArgs& a, hipStream_t s);
+
 // Gaussian-smoothed RDF and its adjoint (smooth.hip).
 constexpr int kSmoothMaxBins = 4096;
 
