@@ -499,6 +499,75 @@ def row_correlation(ppa, hip):
             "lds_atomics_per_s": 3 * pairs / (kern * 1e-3)}
 
 
+def row_steinhardt(ppa, hip):
+    """Q6 and W6 on the k = 12 list of the headline system (the paper's
+    Steinhardt example)."""
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s = workloads.large_fcc()
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    nl = ppa.query_knn(box, pts, 12)
+    out = {"workload": "noisy FCC N=1,048,576 (the headline system), its k=12 NeighborList; "
+                       "Q_l and normalised W_l per particle in float64"}
+    for l, with_w in ((6, False), (6, True), (12, True)):
+        evs = []
+
+        def call():
+            e = hip.events(2)
+            evs.append(e)
+            L.ppa_profile_next(None, None, e[0], e[1])
+            ppa.steinhardt(box, pts, nl, l, with_w=with_w, check=False)
+        timed(call, 10, warmup=2)
+        kern = float(np.mean([hip.ms(e[0], e[1]) for e in evs[2:]]))
+        for e in evs:
+            hip.destroy(e)
+        out[f"l{l}{'_w' if with_w else ''}_kernel_ms"] = kern
+    ql, wl = ppa.steinhardt(box, pts, nl, 6, with_w=True)
+    out["mean_q6"] = float(ql.mean().item())
+    out["mean_w6"] = float(wl.mean().item())
+    out["bonds"] = nl.n_pairs
+    out["bonds_per_s_q6"] = nl.n_pairs / (out["l6_kernel_ms"] * 1e-3)
+    return out
+
+
+def row_clusters(ppa, hip):
+    """Clusters of a 1M-point uniform fluid from its ball list, below and
+    above the percolation threshold."""
+    import numpy as np
+    import torch
+
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s = workloads.uniform(1 << 20, 1.0, seed=640)
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    out = {"workload": "uniform N=1,048,576, density 1; bonds within r_cut from the ball query "
+                       "(r_cut 0.8: about 2.1 bonds per point, below percolation; 1.2: about 7.2, "
+                       "one spanning cluster)"}
+    for r_cut in (0.8, 1.2):
+        nl = ppa.query_ball(box, pts, r_cut)
+        evs = []
+
+        def call():
+            e = hip.events(2)
+            evs.append(e)
+            L.ppa_profile_next(None, None, e[0], e[1])
+            ppa.clusters(nl, 1 << 20, check=False)
+        timed(call, 10, warmup=2)
+        kern = float(np.mean([hip.ms(e[0], e[1]) for e in evs[2:]]))
+        for e in evs:
+            hip.destroy(e)
+        labels, cidx, sizes, k = ppa.clusters(nl, 1 << 20)
+        out[f"r{r_cut}"] = {"bonds": nl.n_pairs, "clusters": k,
+                            "largest": int(sizes.max().item()), "kernels_ms": kern,
+                            "bonds_per_s": nl.n_pairs / (kern * 1e-3)}
+    return out
+
+
 def row_batched(ppa, hip):
     import numpy as np
     import torch
@@ -657,6 +726,8 @@ def main():
         rows["correlation"] = row_correlation(ppa, hip)
         rows["correlation"]["frac_of_lds_atomic_probe"] = (
             rows["correlation"]["lds_atomics_per_s"] / peak["256_bins_per_s"])
+        rows["steinhardt"] = row_steinhardt(ppa, hip)
+        rows["clusters"] = row_clusters(ppa, hip)
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
         rows["paper_context"] = paper_context(ppa)
