@@ -1,10 +1,13 @@
 /*
  * ppa: periodic pair analysis on AMD Instinct MI355X (gfx950).
  *
- * C ABI of libppa.so: neighbor queries in periodic triclinic boxes and the
- * per-bond histograms built from them (RDF, 2D PMFT), after the neighbor
+ * C ABI of libppa.so: neighbor queries in periodic triclinic boxes, the
+ * per-bond histograms built from them (RDF, 2D PMFT, the PMFT over three
+ * pair coordinates, the spatial correlation function) and analyses of a
+ * NeighborList (Steinhardt order parameters, clusters), after the neighbor
  * machinery and analysis modules of the freud paper (arXiv:1906.06317,
- * sections "Implementation" and "Features").
+ * sections "Implementation" and "Features"); plus batched analysis of many
+ * frames and a Gaussian-smoothed RDF with its adjoint.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -28,7 +31,8 @@
  *   return after enqueueing.  Errors found on the host are returned at
  *   once; errors found on the device (non-finite input, output capacity)
  *   are recorded in a status word inside `ws` and returned by
- *   ppa_sync_status, which waits for the stream.
+ *   ppa_sync_status, which waits for the stream.  The status word sits at
+ *   the start of every workspace.
  * Histograms are accumulated into (+=), as the paper's reset=False
  *   accumulation over frames ("Implementation"); zero them to start over.
  * Return value: PPA_OK or a negative PPA_E* code; ppa_last_error() gives a
@@ -481,8 +485,9 @@ int ppa_probe_global_atomics(int32_t log2_words, int32_t iters, int32_t blocks,
                              uint32_t* hist_dev, hipStream_t stream);
 
 /* Waits for the stream and returns the device status of the last call that
- * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE or, for a
- * k-nearest query, PPA_ERANGE). */
+ * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE, for a
+ * k-nearest query PPA_ERANGE, and for ppa_steinhardt / ppa_cluster
+ * PPA_EINVAL when a NeighborList offset or index was out of range). */
 int ppa_sync_status(const void* ws, hipStream_t stream);
 
 /* Message describing the calling thread's last error. */
