@@ -271,7 +271,11 @@ void launch_cluster(const ClusterArgs& a, hipStream_t s)
     // hooking rounds, each flattened, until one changes nothing (later
     // rounds then return at once: no host synchronisation); then the union
     // pass over every bond makes the result exact whatever the rounds left
-    for (int r = 0; r < kClRounds; ++r) {
+    // sparse lists (below about 3 bonds per point, under the percolation
+    // threshold of random geometric graphs) form no large component: the
+    // union pass alone is faster there
+    const int rounds = a.capacity < 3 * (long long)n ? 0 : kClRounds;
+    for (int r = 0; r < rounds; ++r) {
         const int* prev = r > 0 ? a.round_flags + (r - 1) : nullptr;
         hipLaunchKernelGGL(cl_sv_kernel, dim3(nb), dim3(kClBlock), 0, s, a.offsets, a.idx, n,
                            a.capacity, a.labels, prev, a.round_flags + r);
