@@ -165,6 +165,33 @@ int ppa_query_knn(const ppa_box* box, const float* pts, int64_t n, const float* 
                   size_t ws_bytes, int64_t* offsets, int32_t* counts, int32_t* point_idx,
                   float* dist, int64_t* n_pairs_dev, hipStream_t stream);
 
+/* Workspace bytes for ppa_knn_from_nlist on nq rows with this k (host only). */
+int ppa_knn_from_nlist_workspace_bytes(int64_t nq, int32_t k, size_t* bytes);
+
+/* k nearest neighbours selected from a stored NeighborList (the paper's
+ * reuse of a NeighborList across analyses, "Implementation"): each row keeps
+ * its min(k, row length) entries of smallest (distance, point index), in that
+ * order.  For a ball list with cutoff r_max whose rows all hold at least k
+ * entries this equals ppa_query_knn (nothing outside the ball is nearer);
+ * in general it is the k-nearest query guarded at r_max.
+ *   offsets [nq + 1] int64, point_idx [capacity] int32, dist [capacity]
+ *     float32 (all device): the list; an offset outside [0, capacity] or
+ *     decreasing offsets make the row empty and set PPA_EINVAL in the device
+ *     status.
+ *   k in [1, 64]; flags: reserved, must be 0.
+ *   out_offsets [nq + 1] int64 device: CSR row pointer of the result.
+ *   out_counts [nq] int32 device or NULL: row lengths.
+ *   out_idx [nq * k] int32 device, out_dist [nq * k] float32 device or NULL:
+ *     the selected pairs, row after row (out_offsets[nq] of them).
+ *   n_pairs_dev: int64 device, receives out_offsets[nq].
+ * Rows in which more than 256 entries tie at the k-th distance are left
+ * empty and set PPA_ERANGE in the device status. */
+int ppa_knn_from_nlist(const int64_t* offsets, const int32_t* point_idx, const float* dist,
+                       int64_t nq, int64_t capacity, int32_t k, int32_t flags, void* ws,
+                       size_t ws_bytes, int64_t* out_offsets, int32_t* out_counts,
+                       int32_t* out_idx, float* out_dist, int64_t* n_pairs_dev,
+                       hipStream_t stream);
+
 /* Workspace bytes for ppa_pmft2d with these arguments (nq: separate query
  * points, 0 when the points query themselves).  Queries the current device
  * (its compute-unit count and LDS size set the launch) but does no device
@@ -486,8 +513,9 @@ int ppa_probe_global_atomics(int32_t log2_words, int32_t iters, int32_t blocks,
 
 /* Waits for the stream and returns the device status of the last call that
  * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE, for a
- * k-nearest query PPA_ERANGE, and for ppa_steinhardt / ppa_cluster
- * PPA_EINVAL when a NeighborList offset or index was out of range). */
+ * k-nearest query PPA_ERANGE, and for ppa_steinhardt / ppa_cluster /
+ * ppa_knn_from_nlist PPA_EINVAL when a NeighborList offset or index was out
+ * of range, PPA_ERANGE for too many ties in ppa_knn_from_nlist). */
 int ppa_sync_status(const void* ws, hipStream_t stream);
 
 /* Message describing the calling thread's last error. */

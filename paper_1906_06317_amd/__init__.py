@@ -116,6 +116,8 @@ def lib():
             "ppa_steinhardt_workspace_bytes": [i32, i32, ctypes.POINTER(sz)],
             "ppa_steinhardt": [BP, P, i64, P, i64, P, P, i64, i32, i32, P, sz, P, P, P],
             "ppa_cluster_workspace_bytes": [i64, ctypes.POINTER(sz)],
+            "ppa_knn_from_nlist_workspace_bytes": [i64, i32, ctypes.POINTER(sz)],
+            "ppa_knn_from_nlist": [P, P, P, i64, i64, i32, i32, P, sz, P, P, P, P, P, P],
             "ppa_cluster": [P, P, i64, i64, i32, P, sz, P, P, P, P, P],
             "ppa_pmft_xyt_workspace_bytes": [BP, i64, i64, i32, i32, i32, f32, f32, f32,
                                              ctypes.POINTER(sz)],
@@ -702,6 +704,35 @@ def clusters(neighbors, n, ws=None, stream=None, check=True):
         _check(ws.status(stream))
     k = int(nc.item())
     return labels, cidx, sizes[:k], k
+
+
+def knn_from_list(nl: NeighborList, k, ws=None, stream=None, check=True) -> NeighborList:
+    """The k entries of smallest (distance, index) of every row of a stored
+    NeighborList with distances; for a ball list whose rows all hold at least
+    k entries this is the k-nearest query."""
+    torch = _torch()
+    if nl.dist is None:
+        raise ValueError("the list needs its distances")
+    nq = nl.offsets.shape[0] - 1
+    dev = nl.offsets.device
+    need = ctypes.c_size_t(0)
+    _check(lib().ppa_knn_from_nlist_workspace_bytes(nq, int(k), ctypes.byref(need)))
+    ws = ws or default_workspace()
+    wptr, wlen = ws.get(need.value)
+    off = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    counts = torch.empty(max(nq, 1), dtype=torch.int32, device=dev)
+    idx = torch.empty(max(nq * int(k), 1), dtype=torch.int32, device=dev)
+    dist = torch.empty(max(nq * int(k), 1), dtype=torch.float32, device=dev)
+    npairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = nl.point_idx.numel()
+    _check(lib().ppa_knn_from_nlist(_ptr(nl.offsets), _ptr(nl.point_idx) if cap else None,
+                                    _ptr(nl.dist) if cap else None, nq, cap, int(k), 0, wptr,
+                                    wlen, _ptr(off), _ptr(counts), _ptr(idx), _ptr(dist),
+                                    _ptr(npairs), _stream(stream)))
+    if check:
+        _check(ws.status(stream))
+    np_ = int(npairs.item())
+    return NeighborList(off, counts[:nq], idx[:np_], dist[:np_], np_)
 
 
 def smooth_rdf_workspace_bytes(box: Box, n, bins, r_max, sigma):

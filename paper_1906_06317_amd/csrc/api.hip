@@ -1219,6 +1219,81 @@ int ppa_cluster(const int64_t* offsets, const int32_t* point_idx, int64_t n, int
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+static size_t knn_list_layout(int64_t nq, int32_t k, void* base_v, KnnListArgs* A,
+                              unsigned long long** flags, int** ticket, size_t* zero_bytes)
+{
+    char* base = (char*)base_v;
+    size_t off = 256;  // header: status word at 0, scan ticket at 64
+    A->status = (unsigned*)base;
+    *ticket = base ? (int*)(base + 64) : nullptr;
+    *flags = base ? (unsigned long long*)(base + off) : nullptr;
+    off = (off + sizeof(unsigned long long) * scan_flag_count(nq) + 256 + 255) & ~(size_t)255;
+    *zero_bytes = off;
+    A->row_len = base ? (int32_t*)(base + off) : nullptr;
+    off = (off + sizeof(int32_t) * (size_t)nq + 255) & ~(size_t)255;
+    A->out_idx = base ? (int32_t*)(base + off) : nullptr;
+    off = (off + sizeof(int32_t) * (size_t)nq * (size_t)k + 255) & ~(size_t)255;
+    A->out_dist = base ? (float*)(base + off) : nullptr;
+    off = (off + sizeof(float) * (size_t)nq * (size_t)k + 255) & ~(size_t)255;
+    return off;
+}
+
+int ppa_knn_from_nlist_workspace_bytes(int64_t nq, int32_t k, size_t* bytes)
+{
+    if (!bytes) return set_error(PPA_EINVAL, "bytes is NULL");
+    if (nq < 0 || nq > 0x7fffffffLL) return set_error(PPA_EINVAL, "bad row count");
+    if (k < 1 || k > 64) return set_error(PPA_EINVAL, "k must be in [1, 64]");
+    KnnListArgs A{};
+    unsigned long long* flags = nullptr;
+    int* ticket = nullptr;
+    size_t zb = 0;
+    *bytes = knn_list_layout(nq, k, nullptr, &A, &flags, &ticket, &zb);
+    return PPA_OK;
+}
+
+int ppa_knn_from_nlist(const int64_t* offsets, const int32_t* point_idx, const float* dist,
+                       int64_t nq, int64_t capacity, int32_t k, int32_t flags, void* ws,
+                       size_t ws_bytes, int64_t* out_offsets, int32_t* out_counts,
+                       int32_t* out_idx, float* out_dist, int64_t* n_pairs_dev,
+                       hipStream_t stream)
+{
+    size_t need = 0;
+    int rc = ppa_knn_from_nlist_workspace_bytes(nq, k, &need);
+    if (rc) return rc;
+    if (capacity < 0) return set_error(PPA_EINVAL, "negative capacity");
+    if (!offsets) return set_error(PPA_EINVAL, "offsets pointer is NULL");
+    if ((!point_idx || !dist) && capacity > 0)
+        return set_error(PPA_EINVAL, "point_idx and dist of the list are required");
+    if (!out_offsets || !n_pairs_dev || (!out_idx && nq > 0))
+        return set_error(PPA_EINVAL, "out_offsets, out_idx and n_pairs_dev are required");
+    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+        return set_error(PPA_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                         need, ws_bytes);
+    KnnListArgs A{};
+    unsigned long long* scan_flags = nullptr;
+    int* ticket = nullptr;
+    size_t zb = 0;
+    knn_list_layout(nq, k, ws, &A, &scan_flags, &ticket, &zb);
+    if (out_counts) A.row_len = out_counts;
+    A.offsets = offsets;
+    A.idx = point_idx;
+    A.dist = dist;
+    A.nq = nq;
+    A.capacity = capacity;
+    A.k = k;
+    launch_zero_words((unsigned*)ws, (long long)(zb / 4), stream);
+    ProfileEvents pe = take_profile_events();
+    record(pe.ev[2], stream);
+    launch_knn_list(A, knn_list_workgroups(nq), stream);
+    record(pe.ev[3], stream);
+    launch_scan_i64_total(A.row_len, out_offsets, nq, scan_flags, ticket,
+                          (unsigned long long*)n_pairs_dev, stream);
+    launch_knn_pack(nq, k, A.row_len, out_offsets, A.out_idx, A.out_dist, out_idx, out_dist,
+                    stream);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
 int ppa_pmft_xyt_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, int32_t nbx,
                                  int32_t nby, int32_t nbt, float x_max, float y_max, float r_max,
                                  size_t* bytes)
@@ -1306,6 +1381,9 @@ int ppa_sync_status(const void* ws, hipStream_t stream)
     if (st & kStatusCapacity) return set_error(PPA_ECAPACITY, "more pairs than the output capacity");
     if (st & kStatusBadList)
         return set_error(PPA_EINVAL, "a NeighborList offset or point index is out of range");
+    if (st & kStatusTies)
+        return set_error(PPA_ERANGE,
+                         "more than 256 entries of a NeighborList row tie at the k-th distance");
     if (st & kStatusRange)
         return set_error(PPA_ERANGE,
                          "a k-nearest row needs a neighbour at or beyond half the smallest "

@@ -20,6 +20,7 @@ constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusCapacity = 2u;
 constexpr unsigned kStatusRange = 4u;   // a k-nearest row reaches half the box width
 constexpr unsigned kStatusBadList = 8u; // a NeighborList offset or index out of range
+constexpr unsigned kStatusTies = 16u;   // too many list entries tie at the k-th distance
 
 // Box prepared on the host in float64.
 struct BoxPrep {
@@ -327,6 +328,23 @@ struct ClusterArgs {
 };
 
 void launch_cluster(const ClusterArgs& a, hipStream_t s);
+
+// k nearest selected from a stored NeighborList (knn_list.hip).
+struct KnnListArgs {
+    const int64_t* offsets;   // [nq + 1]
+    const int32_t* idx;       // [capacity]
+    const float* dist;        // [capacity]
+    long long nq, capacity;
+    int k;
+    int32_t* row_len;         // [nq] out: min(k, row length)
+    int32_t* out_idx;         // [nq * k] rows at stride k
+    float* out_dist;          // [nq * k]
+    unsigned* status;
+};
+
+int knn_list_workgroups(long long nq);
+void launch_zero_words(unsigned* p, long long words, hipStream_t s);
+void launch_knn_list(const KnnListArgs& a, int blocks, hipStream_t s);
 
 // Gaussian-smoothed RDF and its adjoint (smooth.hip).
 constexpr int kSmoothMaxBins = 4096;
