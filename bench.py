@@ -228,8 +228,10 @@ def headline(args, ppa, hip):
     t1.record()
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
-    count_ms = float(np.mean([hip.ms(e[0], e[1]) for e in ev]))
-    fill_ms = float(np.mean([hip.ms(e[2], e[3]) for e in ev]))
+    count_all = [hip.ms(e[0], e[1]) for e in ev]
+    fill_all = [hip.ms(e[2], e[3]) for e in ev]
+    count_ms = float(np.mean(count_all))
+    fill_ms = float(np.mean(fill_all))
     knn_ms = float(np.mean([hip.ms(e[4], e[5]) for e in ev]))
     for e in ev:
         hip.destroy(e)
@@ -272,7 +274,11 @@ def headline(args, ppa, hip):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "kernel": "fill_kernel (ball list + RDF)", "kernel_ms": fill_ms,
-                     "algorithmic_bytes": alg_bytes, "count_kernel_ms": count_ms},
+                     "algorithmic_bytes": alg_bytes, "count_kernel_ms": count_ms,
+                     "kernel_ms_median": float(np.median(fill_all)),
+                     "kernel_ms_min": float(np.min(fill_all)),
+                     "count_kernel_ms_median": float(np.median(count_all)),
+                     "valu_diagnostic": valu_diagnostic(ppa, box, n, r_max, count_ms, fill_ms)},
     }
     rows = {
         "ball_rdf": {"ms": ball_ms, "pairs_per_s": P / (ball_ms * 1e-3),
@@ -338,6 +344,31 @@ def paper_context(ppa):
                         "100x100 PMFT bins",
             "neighbor_scaling_3d_uniform_density_2.865_r1": scaling,
             "note": "the paper prints no absolute numbers; these are context, not a target"}
+
+
+# Non-packed FP32 lane operations per second of the device: 256 CUs x 64
+# lanes x 2.4 GHz (the packed and dual-issue forms behind the 157.3 TFLOP/s
+# figure are not used by this build's device code).
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+# v_exp_f32 is a quarter-rate transcendental: 16 lanes per CU per clock.
+EXP_PEAK = 256 * 16 * 2.4e9
+
+
+def valu_diagnostic(ppa, box, n, r_max, count_ms, fill_ms):
+    """Candidate evaluations of one pass of the 27-cell stencil (cells of
+    width >= r_max per axis, n / ncells points each), and the lane-operation
+    rate at 4 operations per candidate (three FMAs and a compare of the
+    expanded test) against the non-packed VALU peak."""
+    w = box.widths()
+    cells = 1
+    for k in range(3):
+        cells *= max(1, int(w[k] // (r_max * (1 + 1e-5))))
+    per_query = 27.0 * n / cells
+    evals = per_query * n
+    return {"cells": cells, "candidates_per_query": per_query, "candidate_evaluations": evals,
+            "count_lane_ops_frac": 4 * evals / (count_ms * 1e-3) / VALU_LANE_OPS,
+            "fill_lane_ops_frac": 4 * evals / (fill_ms * 1e-3) / VALU_LANE_OPS,
+            "valu_lane_ops_peak": VALU_LANE_OPS}
 
 
 def lds_atomic_peak(ppa):
@@ -675,12 +706,25 @@ def row_smooth(ppa, hip):
     bwd_ms = timed(bwd, 5, warmup=2)
     if ws.status() != 0:
         raise RuntimeError(L.ppa_last_error().decode())
-    nl = ppa.query_ball(box, pts, r_max + 8 * sigma, with_dist=False)
+    nl = ppa.query_ball(box, pts, r_max + 8 * sigma)
+    # window terms: bins b with |c_b - r| <= 8 sigma, c_b = (b + 1/2) dr, per pair
+    r = nl.dist.double()
+    dr = r_max / bins
+    lo = torch.clamp(torch.ceil((r - 8 * sigma) / dr - 0.5), min=0)
+    hi = torch.clamp(torch.floor((r + 8 * sigma) / dr - 0.5), max=bins - 1)
+    terms = float(torch.clamp(hi - lo + 1, min=0).sum().item())
     return {"workload": "perturbed simple-cubic N=131,072, density 0.9, sigma 0.02, 200 bins on "
                         "[0,3), pairs within 3.16",
             "pairs": nl.n_pairs, "forward_ms": fwd_ms, "adjoint_ms": bwd_ms,
             "forward_pairs_per_s": nl.n_pairs / (fwd_ms * 1e-3),
-            "adjoint_pairs_per_s": nl.n_pairs / (bwd_ms * 1e-3)}
+            "adjoint_pairs_per_s": nl.n_pairs / (bwd_ms * 1e-3),
+            "window_terms": terms,
+            "roofline": {"bound": "alu", "unit": "exp/s", "peak": EXP_PEAK,
+                         "forward_achieved": terms / (fwd_ms * 1e-3),
+                         "forward_frac": terms / (fwd_ms * 1e-3) / EXP_PEAK,
+                         "adjoint_achieved": terms / (bwd_ms * 1e-3),
+                         "adjoint_frac": terms / (bwd_ms * 1e-3) / EXP_PEAK,
+                         "note": "one exp2 per window term (quarter-rate transcendental peak)"}}
 
 
 def main():
