@@ -25,8 +25,11 @@
 // atomics: count_kernel writes row lengths, a scan turns them into CSR
 // offsets, and fill_kernel compacts hits with ballot + mbcnt into a small
 // per-wavefront LDS list of whole rows, flushed densely: the distance, the
-// histogram bin and coalesced stores for 64 hits per instruction.  The RDF
-// alone (no list) needs only the fill pass.  Stencils with more candidates
+// histogram bin and coalesced stores for 64 hits per instruction.  Since the
+// count pass fixed every row's length, the fill pass tests two queries
+// against the same candidate registers at once and places the second row
+// right after the first before either is found; the two independent chains
+// interleave.  The RDF alone (no list) needs only the fill pass.  Stencils with more candidates
 // than the register slots hold are processed in chunks, writing directly.
 #include "pair_common.hpp"
 
@@ -36,9 +39,10 @@ namespace {
 
 using namespace pair;
 
-constexpr int kHitCap = 384;  // hits buffered per wavefront between flushes
+constexpr int kHitCap = 320;  // hits buffered per wavefront between flushes
 constexpr int kRows = 64;     // rows buffered per wavefront
 constexpr int kFillSlots = 10;  // register slots of the fill pass (it needs more registers)
+static_assert(kFillSlots * kWave <= kCandCap, "a whole stencil fits the r^2 buffer");
 constexpr int kMaxBatchLdsBins = 1024;  // per-wavefront histograms of a batch up to this size
 
 // ---------------------------------------------------------------------------
@@ -221,19 +225,19 @@ struct Filler {
             over = true;
         }
     }
-    // Closes the row of query q that started at buffer position rs: a row
-    // with hits gets a record and its start bit (lane 0 writes them).
-    __device__ __forceinline__ void close_row(const Query& q, long long rbase, int rs)
+    // Records a buffered row starting at position rs: query t of the chunk
+    // (its lane holds the point and its row offset rb_v) writes the record
+    // and the row's start bit.
+    __device__ __forceinline__ void add_row(const QueryChunk& Q, long long rb_v, int t, int rs)
     {
         if constexpr (NL) {
-            if (nh > rs) {
-                if (lane == 0) {
-                    W.rq[nrows] = make_float4(q.x, q.y, q.z, __int_as_float(q.id));
-                    W.base[nrows] = rbase - rs;
-                    W.starts[rs >> 6] |= 1ull << (rs & 63);
-                }
-                ++nrows;
+            if (lane == t) {
+                W.rq[nrows] = Q.q;
+                W.base[nrows] = rb_v - rs;
+                // the two rows of a pair may share a word: different lanes
+                atomicOr(&W.starts[rs >> 6], 1ull << (rs & 63));
             }
+            ++nrows;
         }
     }
     // Emits every buffered hit: exact distance, list store and histogram bin.
@@ -300,6 +304,36 @@ struct Filler {
         // removes it from bin 0 at the end
         if (!NL && EXCL == 1) ++selfs;
     }
+    // Buffers the hits of two queries at once: a's row (its length known
+    // from the count pass) at wa, b's at wb, right after it.  The two in/out
+    // chains share the candidate registers and are independent, so their
+    // instructions interleave.
+    template <int NS, bool DOT, bool BY_ID>
+    __device__ __forceinline__ void buffer_pair(const Slots<DIM, NS>& c, const Query& qa,
+                                                const Query& qb, float r2max, int self_a,
+                                                int self_b, int wa, int wb)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            bool ha = c.template hit<DOT>(s, qa, r2max);
+            bool hb = c.template hit<DOT>(s, qb, r2max);
+            if (BY_ID) {
+                ha = ha && c.id[s] != qa.id;
+                hb = hb && c.id[s] != qb.id;
+            }
+            if (!BY_ID && EXCL == 1 && s == 0) {
+                ha = ha && lane != self_a;
+                hb = hb && lane != self_b;
+            }
+            const unsigned long long ma = __ballot(ha);
+            const unsigned long long mb = __ballot(hb);
+            const float4 v = make_float4(c.x[s], c.y[s], c.z[s], __int_as_float(c.id[s]));
+            if (ha) W.hit[wa + (int)lane_prefix(ma)] = v;
+            if (hb) W.hit[wb + (int)lane_prefix(mb)] = v;
+            wa += __popcll(ma);
+            wb += __popcll(mb);
+        }
+    }
     // Writes the hits of query q against NS slots straight to the outputs,
     // at rbase + w onwards.
     template <int NS, bool DOT>
@@ -340,42 +374,70 @@ __device__ __forceinline__ void fill_tile(const PairIn& in, const GeomView& G, c
             rl_v = (int)(F.O.offsets[Q.my_id() + 1] - rb_v);
         }
         for (int t = 0; t < Q.n; ++t) {
-            const Query q = Q.get<DIM>(t, r2max);
-            long long rbase = 0;
-            // entries this query puts in the buffer: its row, plus its own
-            // entry when it is one of the points (dropped at the flush); for
-            // the histogram alone, at most every candidate
-            int need = C;
-            if (NL) {
-                rbase = lane_of64(rb_v, t);
-                need = lane_of(rl_v, t);
-            }
-            const int cap = NL ? kHitCap : kCandCap;
             // position of the query's own entry in slot 0 (home cell first)
             const int self = (c0 - q0) + t < kWave ? (c0 - q0) + t : -1;
-            if (need <= cap) {
-                if (F.nh + need > cap || (NL && F.nrows == kRows)) F.flush();
-                const int rs = F.nh;
-                const bool by_id = EXCL == 2 || (EXCL == 1 && self < 0);
-                if (NL && G.dot) {
-                    if (by_id)
-                        F.template buffer_hits<NS, true, true>(c, q, r2max, self);
+            if constexpr (NL) {
+                const int need = lane_of(rl_v, t);  // the row, from the count pass
+                if (need > kHitCap) {
+                    int w = 0;
+                    const long long rbase = lane_of64(rb_v, t);
+                    if (G.dot)
+                        F.template direct_hits<NS, true>(c, Q.get<DIM>(t, r2max), r2max, rbase, w);
                     else
-                        F.template buffer_hits<NS, true, false>(c, q, r2max, self);
-                } else {
-                    if (by_id)
-                        F.template buffer_hits<NS, false, true>(c, q, r2max, self);
-                    else
-                        F.template buffer_hits<NS, false, false>(c, q, r2max, self);
+                        F.template direct_hits<NS, false>(c, Q.get<DIM>(t, r2max), r2max, rbase, w);
+                    continue;
                 }
-                F.close_row(q, rbase, rs);
+                // two rows at once when both fit the buffer
+                const int need_b = t + 1 < Q.n ? lane_of(rl_v, t + 1) : kHitCap + 1;
+                if (need + need_b <= kHitCap) {
+                    if (F.nh + need + need_b > kHitCap || F.nrows + 2 > kRows) F.flush();
+                    const int rsa = F.nh;
+                    const int rsb = rsa + need;
+                    const int self_b = (c0 - q0) + t + 1 < kWave ? (c0 - q0) + t + 1 : -1;
+                    const bool by_id = EXCL == 2 || (EXCL == 1 && self_b < 0);
+                    const Query qa = Q.get<DIM>(t, r2max);
+                    const Query qb = Q.get<DIM>(t + 1, r2max);
+                    if (G.dot) {
+                        if (by_id)
+                            F.template buffer_pair<NS, true, true>(c, qa, qb, r2max, self, self_b,
+                                                                   rsa, rsb);
+                        else
+                            F.template buffer_pair<NS, true, false>(c, qa, qb, r2max, self, self_b,
+                                                                    rsa, rsb);
+                    } else {
+                        if (by_id)
+                            F.template buffer_pair<NS, false, true>(c, qa, qb, r2max, self,
+                                                                    self_b, rsa, rsb);
+                        else
+                            F.template buffer_pair<NS, false, false>(c, qa, qb, r2max, self,
+                                                                     self_b, rsa, rsb);
+                    }
+                    if (need > 0) F.add_row(Q, rb_v, t, rsa);
+                    if (need_b > 0) F.add_row(Q, rb_v, t + 1, rsb);
+                    F.nh = rsb + need_b;
+                    ++t;
+                    continue;
+                }
+                if (F.nh + need > kHitCap || F.nrows == kRows) F.flush();
             } else {
-                int w = 0;
-                if (G.dot)
-                    F.template direct_hits<NS, true>(c, q, r2max, rbase, w);
-                else
-                    F.template direct_hits<NS, false>(c, q, r2max, rbase, w);
+                // the histogram alone: at most every candidate
+                if (F.nh + C > kCandCap) F.flush();
             }
+            const int rs = F.nh;
+            const bool by_id = EXCL == 2 || (EXCL == 1 && self < 0);
+            const Query q = Q.get<DIM>(t, r2max);
+            if (NL && G.dot) {
+                if (by_id)
+                    F.template buffer_hits<NS, true, true>(c, q, r2max, self);
+                else
+                    F.template buffer_hits<NS, true, false>(c, q, r2max, self);
+            } else {
+                if (by_id)
+                    F.template buffer_hits<NS, false, true>(c, q, r2max, self);
+                else
+                    F.template buffer_hits<NS, false, false>(c, q, r2max, self);
+            }
+            if (NL && F.nh > rs) F.add_row(Q, rb_v, t, rs);
         }
     }
 }
@@ -411,7 +473,7 @@ __device__ __forceinline__ void fill_chunked(const PairIn& in, const GeomView& G
 }
 
 template <int DIM, int EXCL, bool NL, bool HIST>
-__global__ void __launch_bounds__(kBlock, 4) fill_kernel(const PairIn in, const PairGeom G,
+__global__ void __launch_bounds__(kBlock, 5) fill_kernel(const PairIn in, const PairGeom G,
                                                       const FillOut O)
 {
     extern __shared__ unsigned s_hist[];
@@ -583,7 +645,7 @@ __device__ __forceinline__ void merge_wave_hist(unsigned* h, unsigned long long*
 
 // NeighborList and per-frame RDF (histograms [nframes][bins]) of a batch.
 template <int DIM, int EXCL>
-__global__ void __launch_bounds__(kBlock, 4) fill_batch_kernel(const PairIn in, const BatchGeom B,
+__global__ void __launch_bounds__(kBlock, 5) fill_batch_kernel(const PairIn in, const BatchGeom B,
                                                             const FillOut O)
 {
     extern __shared__ unsigned s_dyn[];  // one histogram per wavefront when bins are few
