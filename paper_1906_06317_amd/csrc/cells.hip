@@ -189,11 +189,23 @@ __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restr
 // 2 inclusive prefix) and the value in the low 62.
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
-// items per thread: 2 for short arrays (many tiles in flight), 16 for long
-// ones (few tiles, so the look-back stays within one window)
+// items per thread: 2 for short arrays (many tiles in flight), 4 for long
+// ones (a tile of 4096 items per workgroup, read and written as 16-byte
+// vectors; 2^20 items make 256 tiles, a look-back of at most 4 windows)
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
+
+// Four consecutive outputs (16-byte aligned) in 16-byte stores.
+__device__ __forceinline__ void store4(int* p, int a, int b, int c, int d)
+{
+    *reinterpret_cast<int4*>(p) = make_int4(a, b, c, d);
+}
+__device__ __forceinline__ void store4(int64_t* p, int64_t a, int64_t b, int64_t c, int64_t d)
+{
+    *reinterpret_cast<longlong2*>(p) = make_longlong2(a, b);
+    *reinterpret_cast<longlong2*>(p + 2) = make_longlong2(c, d);
+}
 
 template <typename Out, int kScanItems>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restrict__ in,
@@ -212,12 +224,29 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
     const int64_t base = tile * kTile + (int64_t)threadIdx.x * kScanItems;
     long long v[kScanItems];
     long long sum = 0;
+    // whole, aligned groups of four items move as 16-byte vectors (the
+    // lanes of a wavefront then read one contiguous run)
+    constexpr bool kVec = kScanItems % 4 == 0;
+    const bool vec = kVec && base + kScanItems <= n &&
+                     ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    if (vec) {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        v[k] = i < n ? (long long)in[i] : 0;
-        sum += v[k];
+        for (int k = 0; k < kScanItems; k += 4) {
+            const int4 q = *reinterpret_cast<const int4*>(&in[base + k]);
+            v[k] = q.x;
+            v[k + 1] = q.y;
+            v[k + 2] = q.z;
+            v[k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + k;
+            v[k] = i < n ? (long long)in[i] : 0;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
     // block-wide exclusive scan of per-thread sums
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     long long incl = sum;
@@ -273,18 +302,26 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
     }
     __syncthreads();
     long long run = s_prefix + warp_before + (incl - sum);
+    Out r[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < n) out[i] = (Out)run;
+        r[k] = (Out)run;
         run += v[k];
+    }
+    if (vec) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k += 4) store4(&out[base + k], r[k], r[k + 1], r[k + 2], r[k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < n) out[base + k] = r[k];
     }
 }
 
 }  // namespace
 
 constexpr int kSmallItems = 2;
-constexpr int kLargeItems = 16;
+constexpr int kLargeItems = 4;
 constexpr int64_t kLargeFrom = 64LL * kScanThreads * kSmallItems;
 
 // Status words the scan of n items needs (one per tile of the small size).
