@@ -114,27 +114,9 @@ __device__ __forceinline__ void kl_row(const KnnListArgs& a, long long row, long
             return;
         }
     }
-    // compact the keys under T
+    // compact the keys under T (from the registers, or re-read)
     int nb = 0;
-    const int chunks = NS > 0 ? NS : (L + kWave - 1) / kWave;
-#pragma unroll
-    for (int s = 0; s < chunks; ++s) {
-        float dv;
-        int iv;
-        if (NS > 0) {
-            dv = d[s < NS ? s : 0];
-            iv = id[s < NS ? s : 0];
-#pragma unroll
-            for (int t = 0; t < NS; ++t)
-                if (t == s) {
-                    dv = d[t];
-                    iv = id[t];
-                }
-        } else {
-            const int e = s * kWave + lane;
-            dv = e < L ? a.dist[e0 + e] : INFINITY;
-            iv = e < L ? a.idx[e0 + e] : 0;
-        }
+    auto compact = [&](float dv, int iv) {
         const bool h = dv < T;
         const unsigned long long m = __ballot(h);
         if (h) {
@@ -143,6 +125,15 @@ __device__ __forceinline__ void kl_row(const KnnListArgs& a, long long row, long
             key[nb + (int)below] = kl_key(dv, iv);
         }
         nb += __popcll(m);
+    };
+    if constexpr (NS > 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) compact(d[s], id[s]);
+    } else {
+        for (int b = 0; b < L; b += kWave) {
+            const int e = b + lane;
+            compact(e < L ? a.dist[e0 + e] : INFINITY, e < L ? a.idx[e0 + e] : 0);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
