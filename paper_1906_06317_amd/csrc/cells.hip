@@ -163,20 +163,44 @@ __global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int* __re
 }
 
 // Order each cell's run by point index: every entry counts the entries of its
-// run with a smaller index (its rank) and moves there.
+// run with a smaller index (its rank) and moves there.  The runs a
+// workgroup's entries belong to are contiguous (the entries are sorted by
+// cell), so their indices are staged in LDS once and every count reads LDS;
+// runs spanning more than kRankSpan entries read global memory instead.
+constexpr int kRankSpan = 2048;
+
 __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restrict__ cell_of,
                                                    const int* __restrict__ cell_start,
                                                    const float4* __restrict__ in,
                                                    float4* __restrict__ out)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int s_id[kRankSpan];
+    __shared__ int s_lo, s_hi;
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t p = p0 + threadIdx.x;
+    if (threadIdx.x == 0) {
+        const int64_t last = p0 + blockDim.x - 1 < n ? p0 + blockDim.x - 1 : n - 1;
+        s_lo = cell_start[cell_of[__float_as_int(in[p0].w)]];
+        s_hi = cell_start[cell_of[__float_as_int(in[last].w)] + 1];
+    }
+    __syncthreads();
+    const int lo = s_lo, hi = s_hi;
+    const bool staged = hi - lo <= kRankSpan;
+    if (staged)
+        for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x)
+            s_id[j - lo] = __float_as_int(in[j].w);
+    __syncthreads();
     if (p >= n) return;
     const float4 v = in[p];
     const int id = __float_as_int(v.w);
     const int c = cell_of[id];
     const int b = cell_start[c], e = cell_start[c + 1];
     int r = 0;
-    for (int j = b; j < e; ++j) r += __float_as_int(in[j].w) < id;
+    if (staged) {
+        for (int j = b; j < e; ++j) r += s_id[j - lo] < id;
+    } else {
+        for (int j = b; j < e; ++j) r += __float_as_int(in[j].w) < id;
+    }
     out[b + r] = v;
 }
 
