@@ -255,3 +255,42 @@ def test_small_cutoff_in_sparse_box_uses_exact_test(ppa):
     lo, hi, _ = oracle.rdf_counts(oracle.make_box(s.L, s.tilt), pts, 20, 0.5)
     check_hist(counts.cpu().numpy(), lo, hi)
     assert nl.n_pairs > 500
+
+
+def test_unaligned_output_buffers_large(ppa):
+    """Row counts and offsets at addresses that are not 16-byte aligned (views
+    one element into larger buffers) take the scalar path of the scan's long
+    tiles (2^17 rows and more); the list must equal the one written to
+    aligned buffers, and sampled rows match the oracle."""
+    import ctypes
+    import torch
+    s = workloads.uniform(200_000, 0.8, 1011)
+    box = _box(s)
+    r_max = 1.6
+    ref = ppa.query_ball(box, s.points, r_max)
+    L = ppa.lib()
+    pts = torch.as_tensor(s.points).cuda()
+    n = pts.shape[0]
+    ws = ppa.Workspace()
+    wptr, wlen = ws.get(ppa.workspace_bytes(box, n, 0, r_max, ppa.PPA_WS_NLIST))
+    off_buf = torch.zeros(n + 2, dtype=torch.int64, device="cuda")
+    cnt_buf = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    off, cnt = off_buf[1:], cnt_buf[1:]
+    assert off.data_ptr() % 16 != 0 and cnt.data_ptr() % 16 != 0
+    P = ref.n_pairs
+    pidx = torch.empty(P, dtype=torch.int32, device="cuda")
+    dist = torch.empty(P, dtype=torch.float32, device="cuda")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc = L.ppa_query_ball(ctypes.byref(box.c()), ctypes.c_void_p(pts.data_ptr()), n, None, n,
+                          r_max, 1, 0, wptr, wlen, ctypes.c_void_p(off.data_ptr()),
+                          ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(pidx.data_ptr()),
+                          ctypes.c_void_p(dist.data_ptr()), P, ctypes.c_void_p(npairs.data_ptr()),
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0 and ws.status() == 0
+    assert int(npairs.item()) == P
+    assert torch.equal(off, ref.offsets)
+    assert torch.equal(cnt, (ref.offsets[1:] - ref.offsets[:-1]).to(torch.int32))
+    assert torch.equal(pidx, ref.point_idx[:P]) and torch.equal(dist, ref.dist[:P])
+    assert int(off_buf[0].item()) == 0 and int(cnt_buf[0].item()) == 0  # nothing written before
+    rows = list(range(0, n, 997)) + [n - 1]
+    check_rows(ref, _oracle_rows(s, r_max, rows), rows, r_max)
