@@ -248,6 +248,18 @@ def headline(args, ppa, hip):
                   p(hist), p(offsets), p(rowc), p(pidx), p(dist), P, p(npairs), sptr)
     ball_ms = timed(ball_only, max(5, args.steps // 2))
 
+    # the same call with every row ordered by neighbour index (PPA_SORT_ROWS)
+    def ball_sorted():
+        L.ppa_rdf(ctypes.byref(cb), p(pts), n, None, n, bins, 0.0, r_max, 1, ppa.PPA_SORT_ROWS,
+                  wptr, wlen, p(hist), p(offsets), p(rowc), p(pidx), p(dist), P, p(npairs), sptr)
+    sorted_ms = timed(ball_sorted, max(5, args.steps // 2))
+    srt = pidx[:P]
+    starts = offsets[:-1][offsets[:-1] < P]  # first entry of every non-empty row
+    new_row = torch.zeros(P, dtype=torch.bool, device="cuda").index_fill_(0, starts, True)
+    rows_ok = bool(torch.all((srt[1:] > srt[:-1]) | new_row[1:]).item())
+    if ws.status() != 0 or not rows_ok:
+        raise RuntimeError("sorted rows: device status or order check failed")
+
     # algorithmic bytes of the fill kernel per launch: positions read (12 B per
     # point), row offsets read (8 B per query), neighbour list written (4 B
     # index + 4 B distance per pair), histogram (8 B per bin)
@@ -282,7 +294,9 @@ def headline(args, ppa, hip):
     }
     rows = {
         "ball_rdf": {"ms": ball_ms, "pairs_per_s": P / (ball_ms * 1e-3),
-                     "note": "cell build + count + scan + fill with fused RDF"},
+                     "note": "cell build + count + scan + fill with fused RDF",
+                     "sorted_rows_ms": sorted_ms,
+                     "sort_rows_ms": sorted_ms - ball_ms},
         "knn": {"workload": "same system, k=12 (own cell list)", "ms_in_step": None,
                 "select_kernels_ms": knn_ms, "pairs": n * k},
     }

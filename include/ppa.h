@@ -71,6 +71,14 @@ enum {
  * counts and the scan of the row offsets). */
 #define PPA_WS_NLIST 1
 
+/* Query flag (ppa_query_ball, ppa_rdf with a list): each row of the
+ * NeighborList ordered by neighbour index j, distances moved with their
+ * indices (the paper's promise that the Python API may sort the resulting
+ * neighbours, "Implementation").  Without it a row is in the fixed stencil
+ * order described at ppa_query_ball.  Rows beyond an exceeded capacity are
+ * left as written. */
+#define PPA_SORT_ROWS 2
+
 /* Box from a 3x3 matrix whose columns are the lattice vectors (row-major
  * m[r*3+c]).  The matrix must be upper triangular with a positive diagonal;
  * a general matrix must be rotated into that form by the caller. */
@@ -93,7 +101,7 @@ int ppa_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, float r_cut, 
  * Utilities").
  *   pts [n x 3] device; qpts [nq x 3] device, or NULL to query pts with
  *     themselves (then nq must equal n).
- *   flags: reserved, must be 0.
+ *   flags: 0 or PPA_SORT_ROWS.
  *   offsets [nq + 1] int64 device: CSR row pointer, rows in query order
  *     (the paper's promise of sorted query order); offsets[nq] = pairs.
  *   counts [nq] int32 device or NULL: row lengths.
@@ -103,7 +111,8 @@ int ppa_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, float r_cut, 
  *     exceeds capacity, in which case the status is PPA_ECAPACITY and
  *     point_idx/dist hold an incomplete list).
  * Within a row, pairs are in a fixed order for a given input (stencil cell
- * by stencil cell, then by point index); the output is deterministic.
+ * by stencil cell, then by point index), or by point index with
+ * PPA_SORT_ROWS; the output is deterministic.
  * Two passes: row lengths, a prefix scan into offsets, then the fill. */
 int ppa_query_ball(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
                    float r_max, int32_t exclude_ii, int32_t flags, void* ws, size_t ws_bytes,
@@ -117,7 +126,8 @@ int ppa_query_ball(const ppa_box* box, const float* pts, int64_t n, const float*
  * ppa_query_ball with cutoff r_max.  When offsets is non-NULL the same
  * pass also writes the NeighborList exactly as ppa_query_ball does
  * (neighbours found once, used twice: the paper's lazy iteration of pairs
- * inside the analysis).  counts [bins] uint64 device, accumulated. */
+ * inside the analysis).  counts [bins] uint64 device, accumulated.
+ * flags: 0 or PPA_SORT_ROWS (acts on the list only). */
 int ppa_rdf(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
             int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
             size_t ws_bytes, uint64_t* counts_hist, int64_t* offsets, int32_t* counts,

@@ -27,6 +27,7 @@ PPA_EDEVICE = -5
 PPA_ECAPACITY = -6
 PPA_ENONFINITE = -7
 PPA_WS_NLIST = 1
+PPA_SORT_ROWS = 2
 
 _ERRNAMES = {
     PPA_EINVAL: "PPA_EINVAL", PPA_EBOX: "PPA_EBOX", PPA_ERANGE: "PPA_ERANGE",
@@ -255,7 +256,7 @@ def _estimate_pairs(box: Box, n, nq, r):
 
 
 def _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist, hist, bins,
-               r_min, want_nl, ws, stream, check):
+               r_min, want_nl, ws, stream, check, sort_rows=False):
     torch = _torch()
     pts = _points(points)
     n = pts.shape[0]
@@ -286,6 +287,7 @@ def _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist
         return None
     if capacity is None:
         capacity = _estimate_pairs(box, n, nq, r_max)
+    qflags = PPA_SORT_ROWS if sort_rows else 0
     for attempt in range(2):
         offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
         counts = torch.empty(nq, dtype=torch.int32, device=dev)
@@ -295,12 +297,12 @@ def _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist
         h0 = hist.clone() if (hist is not None and attempt == 0) else None
         if hist is None:
             rc = lib().ppa_query_ball(ctypes.byref(cb), _ptr(pts), n, _ptr(q), nq, float(r_max),
-                                      int(bool(exclude_ii)), 0, wptr, wlen, _ptr(offsets),
+                                      int(bool(exclude_ii)), qflags, wptr, wlen, _ptr(offsets),
                                       _ptr(counts), _ptr(pidx), _ptr(dist), int(capacity),
                                       _ptr(npairs), _stream(stream))
         else:
             rc = lib().ppa_rdf(ctypes.byref(cb), _ptr(pts), n, _ptr(q), nq, int(bins),
-                               float(r_min), float(r_max), int(bool(exclude_ii)), 0, wptr, wlen,
+                               float(r_min), float(r_max), int(bool(exclude_ii)), qflags, wptr, wlen,
                                _ptr(hist), _ptr(offsets), _ptr(counts), _ptr(pidx), _ptr(dist),
                                int(capacity), _ptr(npairs), _stream(stream))
         _check(rc)
@@ -318,22 +320,27 @@ def _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist
 
 
 def query_ball(box: Box, points, r_max, query_points=None, exclude_ii=None, capacity=None,
-               with_dist=True, ws=None, stream=None, check=True) -> NeighborList:
-    """All pairs (i, j) with |p_j - q_i| < r_max under periodic boundaries."""
+               with_dist=True, ws=None, stream=None, check=True,
+               sort_rows=False) -> NeighborList:
+    """All pairs (i, j) with |p_j - q_i| < r_max under periodic boundaries.
+
+    sort_rows=True orders each row by neighbour index j."""
     return _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, with_dist, None, 0,
-                      0.0, True, ws, stream, check)
+                      0.0, True, ws, stream, check, sort_rows)
 
 
 def rdf_counts(box: Box, points, bins, r_max, r_min=0.0, query_points=None, exclude_ii=None,
-               counts=None, neighbor_list=False, capacity=None, ws=None, stream=None, check=True):
+               counts=None, neighbor_list=False, capacity=None, ws=None, stream=None, check=True,
+               sort_rows=False):
     """RDF pair histogram (int64 [bins], accumulated into `counts` when given).
 
-    With neighbor_list=True the same pass also returns the NeighborList."""
+    With neighbor_list=True the same pass also returns the NeighborList
+    (each row ordered by neighbour index with sort_rows=True)."""
     torch = _torch()
     if counts is None:
         counts = torch.zeros(int(bins), dtype=torch.int64, device="cuda")
     nl = _run_pairs(box, points, r_max, query_points, exclude_ii, capacity, True, counts, bins,
-                    r_min, neighbor_list, ws, stream, check)
+                    r_min, neighbor_list, ws, stream, check, sort_rows)
     return (counts, nl) if neighbor_list else counts
 
 

@@ -263,7 +263,7 @@ int run_pairs(const QueryCall& c)
         return set_error(PPA_EINVAL, "nq must equal n when query points are NULL");
     if (!(isfinite(c.r_max) && c.r_max > 0.f))
         return set_error(PPA_EINVAL, "r_max must be finite and positive");
-    if (c.flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", c.flags);
+    if (c.flags & ~PPA_SORT_ROWS) return set_error(PPA_EINVAL, "unknown flags 0x%x", c.flags);
     if (c.want_nl) {
         if (!c.offsets || !c.n_pairs_dev || (!c.point_idx && c.capacity > 0))
             return set_error(PPA_EINVAL, "offsets, point_idx and n_pairs_dev are required");
@@ -332,6 +332,8 @@ int run_pairs(const QueryCall& c)
     record(pe.ev[2], s);
     launch_fill(A, dim, excl, c.want_nl, c.want_hist, s);
     record(pe.ev[3], s);
+    if (c.want_nl && (c.flags & PPA_SORT_ROWS))
+        launch_sort_rows(c.offsets, c.nq, c.point_idx, c.dist, c.capacity, s);
     return hip_check(hipGetLastError(), "kernel launch");
 }
 

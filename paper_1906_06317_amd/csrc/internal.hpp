@@ -161,6 +161,9 @@ void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl,
 // entry), 2 separate query points (drop j == i by index).
 void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s);
 void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s);
+// Orders every complete row of a CSR list by neighbour index (distances follow).
+void launch_sort_rows(const int64_t* offsets, int64_t nq, int32_t* idx, float* dist,
+                      int64_t capacity, hipStream_t s);
 
 // k nearest neighbours (knn.hip).
 struct KnnGeom {

@@ -294,3 +294,71 @@ def test_unaligned_output_buffers_large(ppa):
     assert int(off_buf[0].item()) == 0 and int(cnt_buf[0].item()) == 0  # nothing written before
     rows = list(range(0, n, 997)) + [n - 1]
     check_rows(ref, _oracle_rows(s, r_max, rows), rows, r_max)
+
+
+def _rows_sorted_and_same(nl_sorted, nl_plain):
+    """Every row of nl_sorted is increasing in j and holds the same (j, r)
+    pairs as the same row of nl_plain."""
+    off = nl_plain.offsets.cpu().numpy()
+    assert np.array_equal(off, nl_sorted.offsets.cpu().numpy())
+    pi, pd = nl_plain.point_idx.cpu().numpy(), nl_plain.dist.cpu().numpy()
+    si, sd = nl_sorted.point_idx.cpu().numpy(), nl_sorted.dist.cpu().numpy()
+    n_long = 0
+    for q in range(len(off) - 1):
+        a, b = off[q], off[q + 1]
+        if b - a > 256:
+            n_long += 1
+        assert np.all(np.diff(si[a:b]) > 0), f"row {q} not increasing"
+        order = np.argsort(pi[a:b], kind="stable")
+        assert np.array_equal(si[a:b], pi[a:b][order]), f"row {q}: different neighbours"
+        assert np.array_equal(sd[a:b], pd[a:b][order]), f"row {q}: distances not moved with j"
+    return n_long
+
+
+def test_sort_rows_short_rows_against_oracle(ppa):
+    """sort_rows: rows of about 90 entries (staged in LDS), ordered by j, the
+    oracle's canonical order for the sampled rows."""
+    s = workloads.small_uniform()
+    box = _box(s)
+    plain = ppa.query_ball(box, s.points, 3.0)
+    srt = ppa.query_ball(box, s.points, 3.0, sort_rows=True)
+    assert _rows_sorted_and_same(srt, plain) == 0
+    rows = list(range(0, 4096, 37))
+    check_rows(srt, _oracle_rows(s, 3.0, rows), rows, 3.0)
+    # the oracle lists each row by increasing j: the certain part matches in order
+    o_off, o_idx, o_r2 = _oracle_rows(s, 3.0, rows)
+    off = srt.offsets.cpu().numpy()
+    pidx = srt.point_idx.cpu().numpy()
+    lo = 9.0 * (1 - REL)
+    for k, q in enumerate(rows):
+        oi, orr = o_idx[o_off[k]:o_off[k + 1]], o_r2[o_off[k]:o_off[k + 1]]
+        certain = np.sort(oi[orr < lo])
+        g = pidx[off[q]:off[q + 1]]
+        assert np.array_equal(g[np.isin(g, certain)], certain)
+
+
+def test_sort_rows_long_rows_bitonic(ppa):
+    """Rows longer than the LDS stage (256) are sorted in place by the bitonic
+    network; lengths are not powers of two.  Separate query points too."""
+    s = workloads.uniform(6000, 8.0, 1012)   # r = 2.7: about 660 neighbours per point
+    box = _box(s)
+    plain = ppa.query_ball(box, s.points, 2.7)
+    srt = ppa.query_ball(box, s.points, 2.7, sort_rows=True)
+    assert _rows_sorted_and_same(srt, plain) > 1000
+    q = workloads.uniform(500, 8.0, 1013, L=s.L).points
+    plain = ppa.query_ball(box, s.points, 2.7, query_points=q)
+    srt = ppa.query_ball(box, s.points, 2.7, query_points=q, sort_rows=True)
+    assert _rows_sorted_and_same(srt, plain) > 100
+
+
+def test_sort_rows_with_rdf_and_capacity_retry(ppa):
+    """The RDF pass with its list sorted: the histogram is unchanged, the
+    list sorted; a first attempt with too small a capacity is retried."""
+    import torch
+    s = workloads.small_uniform()
+    box = _box(s)
+    h0, plain = ppa.rdf_counts(box, s.points, 100, 3.0, neighbor_list=True)
+    h1, srt = ppa.rdf_counts(box, s.points, 100, 3.0, neighbor_list=True, sort_rows=True,
+                             capacity=1000)
+    assert torch.equal(h0, h1)
+    _rows_sorted_and_same(srt, plain)

@@ -103,6 +103,8 @@ def test_query_argument_errors_before_any_device_work():
     assert _call_ball(box, r=-1.0) == ppa.PPA_EINVAL
     assert _call_ball(box, r=float("nan")) == ppa.PPA_EINVAL
     assert _call_ball(box, flags=8) == ppa.PPA_EINVAL
+    assert _call_ball(box, flags=1) == ppa.PPA_EINVAL             # a workspace flag, not a query flag
+    assert _call_ball(box, flags=ppa.PPA_SORT_ROWS, r=6.0) == ppa.PPA_ERANGE  # flag accepted
     assert _call_ball(box, offsets=0) == ppa.PPA_EINVAL
     assert _call_ball(box, cap=-1) == ppa.PPA_EINVAL
     assert _call_ball(box, r=6.0) == ppa.PPA_ERANGE
