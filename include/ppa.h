@@ -431,7 +431,8 @@ typedef struct ppa_batch_graph_s ppa_batch_graph;
  * non-decreasing, N = frame_offsets[n_frames] < 2^31).  All frames share
  * the dimension, bins, r_min, r_max and exclude_ii (each frame's points
  * query themselves).  r_max must be below half the smallest perpendicular
- * width of every frame (PPA_ERANGE names the frame).  flags: reserved, 0.
+ * width of every frame (PPA_ERANGE names the frame).  flags: 0 or
+ * PPA_SORT_ROWS (every run orders each row by frame-local neighbour index).
  * Host only; free with ppa_batch_plan_destroy. */
 int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t* frame_offsets,
                           int32_t bins, float r_min, float r_max, int32_t exclude_ii,

@@ -843,7 +843,7 @@ class BatchPlan:
     with frame-local point indices); graph() captures a run in a HIP graph."""
 
     def __init__(self, boxes, frame_sizes, bins, r_max, r_min=0.0, exclude_ii=True,
-                 capacity=None):
+                 capacity=None, sort_rows=False):
         torch = _torch()
         self.boxes = list(boxes)
         sizes = np.asarray(frame_sizes, dtype=np.int64)
@@ -859,7 +859,8 @@ class BatchPlan:
         _check(lib().ppa_batch_plan_create(self.n_frames, cboxes,
                                            self.offsets_host.ctypes.data_as(ctypes.c_void_p),
                                            self.bins, self.r_min, self.r_max,
-                                           int(bool(exclude_ii)), 0, ctypes.byref(h)))
+                                           int(bool(exclude_ii)),
+                                           PPA_SORT_ROWS if sort_rows else 0, ctypes.byref(h)))
         self._h = h
         need = ctypes.c_size_t(0)
         _check(lib().ppa_batch_workspace_bytes(self._h, ctypes.byref(need)))

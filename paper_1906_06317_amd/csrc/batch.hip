@@ -48,6 +48,7 @@ struct ppa_batch_plan_s {
     float r_min, r_max;
     int excl;
     int64_t n_total;
+    bool sort_rows;               // PPA_SORT_ROWS: rows ordered by neighbour index
     std::vector<int> point_base;  // [nframes + 1]
     ConfigTables cfg[kNumConfigs];
     int chosen;
@@ -149,6 +150,8 @@ void enqueue(const ppa_batch_plan* p, int ci, const float* pts, void* ws, const 
     launch_scan_i64_total(A.counts, o.offsets, p->n_total, W.row_scan_flags, W.row_scan_ticket,
                           (unsigned long long*)o.n_pairs_dev, s);
     launch_fill_batch(A, B, p->dim, p->excl, cap, s);
+    if (p->sort_rows)
+        launch_sort_rows(o.offsets, p->n_total, o.point_idx, o.dist, o.capacity, s);
 }
 
 int check_out(const RunOut& o)
@@ -171,7 +174,7 @@ int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t*
     *out = nullptr;
     if (n_frames < 1 || !boxes || !frame_offsets)
         return set_error(PPA_EINVAL, "need at least one frame, its box and offsets");
-    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~PPA_SORT_ROWS) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
     if (bins < 1) return set_error(PPA_EINVAL, "bins must be >= 1");
     if (!(isfinite(r_max) && r_max > 0.f && isfinite(r_min) && r_min >= 0.f && r_min < r_max))
         return set_error(PPA_EINVAL, "need 0 <= r_min < r_max");
@@ -201,6 +204,7 @@ int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t*
     p->r_max = r_max;
     p->excl = exclude_ii ? 1 : 0;
     p->n_total = frame_offsets[n_frames];
+    p->sort_rows = (flags & PPA_SORT_ROWS) != 0;
     p->point_base.resize(n_frames + 1);
     for (int f = 0; f <= n_frames; ++f) p->point_base[f] = (int)frame_offsets[f];
     p->chosen = 0;

@@ -204,3 +204,34 @@ def test_non_finite_and_capacity_are_reported(ppa):
         small.run(pts2)
     assert e.value.code == ppa.PPA_ECAPACITY
     assert int(small.n_pairs.item()) > 1000  # the true count is still reported
+
+
+def test_sorted_rows_and_graph(ppa):
+    """A plan with sort_rows: every row ordered by frame-local neighbour
+    index, holding the unsorted run's pairs; the oracle's rows match; a graph
+    replay gives the same sorted list."""
+    import torch
+    frames = _frames(16, 6, 1000, 6000)
+    plain, pts = _plan(ppa, frames)
+    srt, _ = _plan(ppa, frames, sort_rows=True)
+    p = torch.as_tensor(pts).cuda()
+    h0, nl0 = plain.run(p)
+    h1, nl1 = srt.run(p)
+    assert torch.equal(h0, h1)
+    off = nl0.offsets.cpu().numpy()
+    assert np.array_equal(off, nl1.offsets.cpu().numpy())
+    pi, pd = nl0.point_idx.cpu().numpy(), nl0.dist.cpu().numpy()
+    si, sd = nl1.point_idx.cpu().numpy(), nl1.dist.cpu().numpy()
+    for q in range(len(off) - 1):
+        a, b = off[q], off[q + 1]
+        assert np.all(np.diff(si[a:b]) > 0), f"row {q} not increasing"
+        order = np.argsort(pi[a:b], kind="stable")
+        assert np.array_equal(si[a:b], pi[a:b][order]) and np.array_equal(sd[a:b], pd[a:b][order])
+    _check_against_oracle(frames, h1, nl1, srt.offsets_host, which=[0, 3])
+    hist = torch.zeros((len(frames), BINS), dtype=torch.int64, device="cuda")
+    launch = srt.graph(p, hist)
+    for _ in range(2):
+        launch()
+        torch.cuda.synchronize()
+        assert srt.ws.status() == 0
+        np.testing.assert_array_equal(srt.neighbor_list().point_idx.cpu().numpy(), si)
