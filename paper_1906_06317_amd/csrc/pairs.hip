@@ -217,12 +217,10 @@ struct Filler {
     __device__ __forceinline__ void emit(long long dst, int id, float r)
     {
         if (dst < O.capacity) {
-            // plain stores: the partial lines at the two ends of each row
-            // segment meet in L2 and leave it whole (non-temporal stores
-            // wrote 720 MB per launch of the 2^20-point FCC list instead of
-            // 595 MB, for 77 MB fewer stencil re-reads and the same time)
-            O.point_idx[dst] = id - id_base;
-            if (O.dist) O.dist[dst] = r;
+            // the list is written once and read by a later kernel: stream it
+            // past the caches, which keep the stencil cells
+            __builtin_nontemporal_store(id - id_base, &O.point_idx[dst]);
+            if (O.dist) __builtin_nontemporal_store(r, &O.dist[dst]);
         } else {
             over = true;
         }
