@@ -355,6 +355,13 @@ int ppa_steinhardt(const ppa_box* box, const float* pts, int64_t n, const float*
                    int32_t flags, void* ws, size_t ws_bytes, double* ql, double* wl,
                    hipStream_t stream);
 
+/* Cluster flag: the list is symmetric (j in row i exactly when i is in row
+ * j, as in a ball query of the points with themselves).  The hooking rounds
+ * then sample two bonds per row and the closing union pass skips the points
+ * of the largest sampled component.  The labels are the same; with a list
+ * that is not symmetric they may be wrong. */
+#define PPA_CLUSTER_SYMMETRIC 1
+
 /* Workspace bytes for ppa_cluster on n points (host only). */
 int ppa_cluster_workspace_bytes(int64_t n, size_t* bytes);
 
@@ -368,7 +375,7 @@ int ppa_cluster_workspace_bytes(int64_t n, size_t* bytes);
  *     with themselves).  An offset outside [0, capacity], decreasing
  *     offsets or an index outside [0, n) is skipped and sets the device
  *     status to PPA_EINVAL.
- *   flags: reserved, must be 0.
+ *   flags: 0 or PPA_CLUSTER_SYMMETRIC.
  *   labels [n] int32 device: the smallest point index of each point's
  *     component (deterministic, independent of scheduling).
  *   cluster_idx [n] int32 device or NULL: components numbered 0, 1, ... in

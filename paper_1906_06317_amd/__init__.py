@@ -28,6 +28,7 @@ PPA_ECAPACITY = -6
 PPA_ENONFINITE = -7
 PPA_WS_NLIST = 1
 PPA_SORT_ROWS = 2
+PPA_CLUSTER_SYMMETRIC = 1
 
 _ERRNAMES = {
     PPA_EINVAL: "PPA_EINVAL", PPA_EBOX: "PPA_EBOX", PPA_ERANGE: "PPA_ERANGE",
@@ -678,11 +679,16 @@ def steinhardt(box: Box, points, neighbors, l, query_points=None, with_w=False, 
     return ql, wl
 
 
-def clusters(neighbors, n, ws=None, stream=None, check=True):
+def clusters(neighbors, n, ws=None, stream=None, check=True, symmetric=False):
     """Connected components of a NeighborList over n points (bonds as
     undirected edges): (labels, cluster_idx, sizes, n_clusters) with labels
     the smallest index of each point's component, cluster_idx the components
-    numbered by that index, sizes[:n_clusters] their point counts."""
+    numbered by that index, sizes[:n_clusters] their point counts.
+
+    symmetric=True declares that j is in row i exactly when i is in row j
+    (a ball query of the points with themselves), which lets large
+    components form faster; with a list that is not symmetric the labels
+    may be wrong."""
     torch = _torch()
     if isinstance(neighbors, NeighborList):
         off, idx = neighbors.offsets, neighbors.point_idx
@@ -704,7 +710,8 @@ def clusters(neighbors, n, ws=None, stream=None, check=True):
     _check(lib().ppa_cluster_workspace_bytes(n, ctypes.byref(need)))
     ws = ws or default_workspace()
     wptr, wlen = ws.get(need.value)
-    _check(lib().ppa_cluster(_ptr(off), _ptr(idx) if idx.numel() else None, n, idx.numel(), 0,
+    _check(lib().ppa_cluster(_ptr(off), _ptr(idx) if idx.numel() else None, n, idx.numel(),
+                             PPA_CLUSTER_SYMMETRIC if symmetric else 0,
                              wptr, wlen, _ptr(labels) if n else None, _ptr(cidx) if n else None,
                              _ptr(sizes) if n else None, _ptr(nc), _stream(stream)))
     if check:

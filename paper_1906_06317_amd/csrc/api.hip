@@ -1170,7 +1170,8 @@ static size_t cluster_layout(int64_t n, void* base_v, ClusterArgs* A)
     A->status = (unsigned*)base;
     A->ticket = base ? (int*)(base + 64) : nullptr;
     A->round_flags = base ? (int*)(base + 128) : nullptr;  // kClusterRounds ints
-    static_assert(128 + 4 * kClusterRounds <= 256, "round flags exceed the header");
+    static_assert(128 + 4 * kClusterRounds <= 192, "round flags exceed their part of the header");
+    A->giant = base ? (int*)(base + 192) : nullptr;
     A->scan_flags = base ? (unsigned long long*)(base + off) : nullptr;
     off = (off + flag_bytes + 255) & ~(size_t)255;
     A->zero = (unsigned*)base;
@@ -1199,7 +1200,7 @@ int ppa_cluster(const int64_t* offsets, const int32_t* point_idx, int64_t n, int
     if (!offsets) return set_error(PPA_EINVAL, "offsets pointer is NULL");
     if (!point_idx && capacity > 0) return set_error(PPA_EINVAL, "point_idx pointer is NULL");
     if (!labels && n > 0) return set_error(PPA_EINVAL, "labels pointer is NULL");
-    if (flags != 0) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~PPA_CLUSTER_SYMMETRIC) return set_error(PPA_EINVAL, "unknown flags 0x%x", flags);
     ClusterArgs A{};
     const size_t need = cluster_layout(n, nullptr, &A);
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
@@ -1214,6 +1215,7 @@ int ppa_cluster(const int64_t* offsets, const int32_t* point_idx, int64_t n, int
     A.cluster_idx = cluster_idx;
     A.sizes = sizes;
     A.n_clusters = n_clusters_dev;
+    A.symmetric = (flags & PPA_CLUSTER_SYMMETRIC) ? 1 : 0;
     ProfileEvents pe = take_profile_events();
     record(pe.ev[2], stream);
     launch_cluster(A, stream);

@@ -323,6 +323,8 @@ struct ClusterArgs {
     unsigned* status;         // workspace header
     int* ticket;              // scan tile ticket (workspace header)
     int* round_flags;         // [kClusterRounds] changes per hooking round (header)
+    int* giant;               // root of the sampled largest component (header)
+    int symmetric;            // every bond is listed in both rows
     unsigned long long* scan_flags;
     int* is_root;             // [n]
     int64_t* rank;            // [n + 1]

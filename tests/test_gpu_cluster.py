@@ -129,3 +129,44 @@ def test_synthetic_graph_1m_against_oracle(ppa):
     idx = np.where(keep, idx, rows).astype(np.int32)  # some self bonds (ignored)
     k = _compare(ppa, n, off, idx)
     assert 1000 < k < n
+
+
+def _compare_symmetric(ppa, n, off, idx):
+    """The symmetric-list path against the oracle."""
+    labels, cidx, sizes, k = ppa.clusters((off, idx), n, symmetric=True)
+    ol, oc, os_ = oracle.clusters(n, off, idx)
+    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
+    np.testing.assert_array_equal(cidx.cpu().numpy(), oc)
+    np.testing.assert_array_equal(sizes.cpu().numpy(), os_)
+    return k
+
+
+@pytest.mark.parametrize("dim,density,r_cut", [(3, 0.9, 0.75), (3, 0.9, 0.95), (3, 0.9, 1.4),
+                                               (2, 0.8, 0.8), (2, 0.8, 1.2)])
+def test_symmetric_flag_against_oracle(ppa, dim, density, r_cut):
+    """Oracle ball lists (symmetric): below, near and above percolation, the
+    sampled-rounds path gives the oracle's components."""
+    s = workloads.uniform(4000, density, seed=620 + dim, dim=dim, tilt=(0.2, -0.1, 0.15))
+    off, idx, _ = oracle.ball_query(oracle.make_box(s.L, s.tilt, dim), s.points, r_cut)
+    assert _compare_symmetric(ppa, 4000, off, idx.astype(np.int32)) >= 1
+
+
+@pytest.mark.parametrize("r_cut", [0.8, 1.2, 1.6])
+def test_symmetric_flag_same_labels_1m(ppa, r_cut):
+    """N = 1,048,576 uniform, GPU ball lists below and above percolation: the
+    flagged call returns exactly the unflagged labels, and the labels hold the
+    properties any size has (bonded points share a label, a label names a
+    member that labels itself)."""
+    s = workloads.uniform(1 << 20, 1.0, seed=640)
+    nl = ppa.query_ball(_box(s), s.points, r_cut)
+    a = ppa.clusters(nl, 1 << 20)
+    b = ppa.clusters(nl, 1 << 20, symmetric=True)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    assert a[3] == b[3]
+    lab = b[0].cpu().numpy()
+    off = nl.offsets.cpu().numpy()
+    idx = nl.point_idx.cpu().numpy()
+    rows = np.repeat(np.arange(1 << 20), np.diff(off))
+    assert np.all(lab[rows] == lab[idx])
+    assert np.all(lab <= np.arange(1 << 20)) and np.all(lab[lab] == lab)

@@ -221,3 +221,14 @@ def test_pmft_workspace_and_errors():
     with pytest.raises(ppa.PPAError) as e:
         ppa.pmft2d_workspace_bytes(b2, 1000, 0, 50, 50, 3.0, 3.0, 10.0)
     assert e.value.code == ppa.PPA_ERANGE
+
+
+def test_cluster_flags_and_workspace_errors():
+    L = ppa.lib()
+    off = ctypes.c_void_p(256)  # never read: the host checks come first
+    args = lambda flags, ws: L.ppa_cluster(off, ctypes.c_void_p(512), 10, 20, flags, ws,
+                                           1 << 20, ctypes.c_void_p(1024), None, None, None,
+                                           None)
+    assert args(2, ctypes.c_void_p(4096)) == ppa.PPA_EINVAL          # unknown flag
+    assert args(ppa.PPA_CLUSTER_SYMMETRIC, None) == ppa.PPA_EWORKSPACE  # flag accepted
+    assert args(0, ctypes.c_void_p(4096 + 8)) == ppa.PPA_EWORKSPACE  # misaligned
