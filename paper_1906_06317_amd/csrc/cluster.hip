@@ -255,36 +255,58 @@ __global__ void __launch_bounds__(kClBlock) cl_compress_kernel(int n, int* label
     if (is_root) is_root[i] = r == i ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(kClBlock) cl_index_kernel(int n, const int* __restrict__ labels,
-                                                            const int64_t* __restrict__ rank,
-                                                            int32_t* cluster_idx, int32_t* sizes)
+constexpr int kClIndexBlock = 1024;
+
+__global__ void __launch_bounds__(kClIndexBlock) cl_index_kernel(int n,
+                                                                 const int* __restrict__ labels,
+                                                                 const int64_t* __restrict__ rank,
+                                                                 int32_t* cluster_idx,
+                                                                 int32_t* sizes)
 {
-    const int i = blockIdx.x * kClBlock + threadIdx.x;
-    if (i >= n) return;
-    const int c = (int)rank[labels[i]];
-    if (cluster_idx) cluster_idx[i] = c;
-    if (sizes) {
-        // one atomic per distinct cluster of the wavefront: the points of a
-        // large cluster would otherwise all add to the same counter
-        // the few clusters most of the wavefront shares get one atomic each
-        // (a large cluster would otherwise have all its points add to one
-        // counter); after four rounds the rest add one by one
-        bool done = false;
-        for (int round = 0; round < 4; ++round) {
-            if (!done) {
-                // the first lane not yet counted names the cluster of this round
-                const int c0 = __builtin_amdgcn_readfirstlane(c);
-                const unsigned long long m = __ballot(c == c0);
-                if (c == c0) {
-                    const unsigned below = __builtin_amdgcn_mbcnt_hi(
-                        (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    if (below == 0) atomicAdd(&sizes[c0], __popcll(m));
-                    done = true;
-                }
-            }
-        }
-        if (!done) atomicAdd(&sizes[c], 1);
+    __shared__ int s_c[kClIndexBlock / 64], s_n[kClIndexBlock / 64];
+    const int i = blockIdx.x * kClIndexBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool live = i < n;
+    const int c = live ? (int)rank[labels[i]] : -1;
+    if (live && cluster_idx) cluster_idx[i] = c;
+    if (!sizes) return;
+    // the cluster of each wavefront's first point is counted for the whole
+    // workgroup: the wavefronts that share it (all of them inside a large
+    // cluster) add one total with one atomic
+    const int c0 = __builtin_amdgcn_readfirstlane(c);
+    const unsigned long long m0 = __ballot(live && c == c0);
+    if (lane == 0) {
+        s_c[wv] = c0;
+        s_n[wv] = __popcll(m0);
     }
+    __syncthreads();
+    if (threadIdx.x < kClIndexBlock / 64) {
+        const int w = threadIdx.x;
+        // the first wavefront holding this cluster adds for all that hold it
+        int first = w, total = 0;
+        for (int u = 0; u < kClIndexBlock / 64; ++u)
+            if (s_c[u] == s_c[w]) {
+                if (u < first) first = u;
+                total += s_n[u];
+            }
+        if (first == w && s_c[w] >= 0 && total > 0) atomicAdd(&sizes[s_c[w]], total);
+    }
+    // the other points: one atomic per distinct cluster of the wavefront for
+    // three more rounds, then one by one
+    bool done = !live || c == c0;
+    for (int round = 0; round < 3; ++round) {
+        const unsigned long long pend = __ballot(!done);
+        if (!pend) break;
+        const int cr = __builtin_amdgcn_readlane(c, __ffsll((unsigned long long)pend) - 1);
+        const unsigned long long m = __ballot(!done && c == cr);
+        if (!done && c == cr) {
+            const unsigned below = __builtin_amdgcn_mbcnt_hi(
+                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (below == 0) atomicAdd(&sizes[cr], __popcll(m));
+            done = true;
+        }
+    }
+    if (!done) atomicAdd(&sizes[c], 1);
 }
 
 inline int blocks_for(long long n) { return (int)((n + kClBlock - 1) / kClBlock); }
@@ -344,7 +366,8 @@ void launch_cluster(const ClusterArgs& a, hipStream_t s)
     launch_scan_i64_total(a.is_root, a.rank, n, a.scan_flags, a.ticket,
                           (unsigned long long*)a.n_clusters, s);
     if (a.cluster_idx || a.sizes)
-        hipLaunchKernelGGL(cl_index_kernel, dim3(blocks_for(n)), dim3(kClBlock), 0, s, n, a.labels,
+        hipLaunchKernelGGL(cl_index_kernel, dim3((n + kClIndexBlock - 1) / kClIndexBlock),
+                           dim3(kClIndexBlock), 0, s, n, a.labels,
                            a.rank, a.cluster_idx, a.sizes);
 }
 
