@@ -362,3 +362,18 @@ def test_sort_rows_with_rdf_and_capacity_retry(ppa):
                              capacity=1000)
     assert torch.equal(h0, h1)
     _rows_sorted_and_same(srt, plain)
+
+
+def test_sort_rows_without_distances(ppa):
+    """sort_rows with no distance output (with_dist=False): indices only,
+    short rows (LDS) and long rows (bitonic) alike."""
+    for s, r in ((workloads.small_uniform(), 3.0), (workloads.uniform(3000, 8.0, 1014), 2.7)):
+        box = _box(s)
+        plain = ppa.query_ball(box, s.points, r, with_dist=False)
+        srt = ppa.query_ball(box, s.points, r, with_dist=False, sort_rows=True)
+        assert srt.dist is None
+        off = plain.offsets.cpu().numpy()
+        pi, si = plain.point_idx.cpu().numpy(), srt.point_idx.cpu().numpy()
+        for q in range(len(off) - 1):
+            a, b = off[q], off[q + 1]
+            assert np.array_equal(si[a:b], np.sort(pi[a:b])), f"row {q}"
