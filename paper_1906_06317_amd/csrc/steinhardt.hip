@@ -71,8 +71,12 @@ __device__ __forceinline__ double2 q_of(const double2* q, int m)
     return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
 }
 
+// Five wavefronts per SIMD for l <= 6 (96 VGPRs: Q6 with W6 on the k = 12
+// list of the 2^20-point FCC 0.217 -> 0.203 ms); larger l keep their
+// registers (l = 8 at five wavefronts spills; l = 12 bounded to four
+// spilled and took 0.80 ms instead of 0.66).
 template <int L>
-__global__ void __launch_bounds__(kStBlock) steinhardt_kernel(const SteinArgs a)
+__global__ void __launch_bounds__(kStBlock, (L <= 6 ? 5 : 1)) steinhardt_kernel(const SteinArgs a)
 {
     const long long i = (long long)blockIdx.x * kStBlock + threadIdx.x;
     if (i >= a.nq) return;
