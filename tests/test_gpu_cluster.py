@@ -170,3 +170,27 @@ def test_symmetric_flag_same_labels_1m(ppa, r_cut):
     rows = np.repeat(np.arange(1 << 20), np.diff(off))
     assert np.all(lab[rows] == lab[idx])
     assert np.all(lab <= np.arange(1 << 20)) and np.all(lab[lab] == lab)
+
+
+def test_symmetric_flag_small_and_bad_lists(ppa):
+    """The symmetric path on degenerate inputs: an empty list, a list with an
+    out-of-range index and enough bonds for the hooking rounds to run
+    (reported, no fault), and a long symmetric chain (one component whose
+    sampled bonds form a path)."""
+    labels, cidx, sizes, k = ppa.clusters((np.zeros(6, np.int64), np.zeros(0, np.int32)), 5,
+                                          symmetric=True)
+    np.testing.assert_array_equal(labels.cpu().numpy(), np.arange(5))
+    assert k == 5
+    with pytest.raises(ppa.PPAError) as e:
+        ppa.clusters((np.array([0, 3, 6], np.int64), np.array([1, 7, 1, 0, 9, 0], np.int32)), 2,
+                     symmetric=True)
+    assert e.value.code == ppa.PPA_EINVAL
+    n = 3000  # chain 0 - 1 - ... - n-1 and a separate chain of the last 500 points
+    rows = []
+    for i in range(n):
+        nb = [j for j in (i - 1, i + 1) if 0 <= j < n and not ((i < 2500) ^ (j < 2500))]
+        rows.append(nb + nb)  # listed twice: four entries, so the rounds run
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    idx = np.concatenate([np.array(r, np.int32) for r in rows])
+    k = _compare_symmetric(ppa, n, off, idx)
+    assert k == 2
