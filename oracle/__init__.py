@@ -66,6 +66,8 @@ def lib():
             "orc_ball_count": [BP, P, i64, P, i64, f64, i32, P],
             "orc_ball_fill": [BP, P, i64, P, i64, f64, i32, P, P, P],
             "orc_rdf": [BP, P, i64, P, i64, i64, f64, f64, i32, f64, P, P, P],
+            "orc_ball_rdf_rows": [BP, P, i64, P, i64, i64, f64, i32, i64, P, P, P, i64, f64, f64,
+                                  f64, P, P, P],
             "orc_knn": [BP, P, i64, P, i64, i32, i32, i32, f64, P, P, P],
             "orc_pmft2d": [BP, P, i64, P, P, i64, i64, i64, f64, f64, f64, i32, f64, f64, P, P, P],
             "orc_correlation": [BP, P, P, i64, P, P, i64, i64, f64, f64, i32, f64, P, P, P, P, P],
@@ -155,6 +157,38 @@ def rdf_counts(box: Box, points, bins: int, r_max: float, r_min: float = 0.0,
     lib().orc_rdf(ctypes.byref(box), _p(pts), pts.shape[0], _p(q), q.shape[0], bins,
                   float(r_min), float(r_max), int(exclude_ii), rel_band, _p(lo), _p(hi), _p(amb))
     return lo, hi, int(amb[0])
+
+
+def ball_rdf_rows(box: Box, points, r_max: float, bins: int, rows=None, exclude_ii=True,
+                  cap: int = 256, r_min: float = 0.0, lo=None, hi=None, n_amb=None,
+                  rel_band: float = REL_BAND):
+    """Self-query rows [a, b) of the ball query and their RDF bounds in one sweep.
+
+    Returns (counts int64[m], idx int32[m, cap], r2 float64[m, cap]) for the
+    m = b - a rows (each row's points with r^2 < r_max^2 (1 + rel_band), in
+    ascending index, padded past counts), and accumulates the rows' RDF pairs
+    into lo / hi (uint64[bins]) and n_amb (uint64[1]), allocated when None and
+    returned as (counts, idx, r2, lo, hi, n_amb).  A row longer than cap
+    raises."""
+    pts = _f32(points)
+    n = pts.shape[0]
+    a, b = (0, n) if rows is None else (int(rows[0]), int(rows[1]))
+    q = np.ascontiguousarray(pts[a:b])
+    m = b - a
+    if lo is None:
+        lo = np.zeros(bins, np.uint64)
+        hi = np.zeros(bins, np.uint64)
+        n_amb = np.zeros(1, np.uint64)
+    counts = np.zeros(m, np.int64)
+    idx = np.full((m, cap), -1, np.int32)
+    r2 = np.full((m, cap), np.inf, np.float64)
+    rc = lib().orc_ball_rdf_rows(ctypes.byref(box), _p(pts), n, _p(q), m, a,
+                                 float(r_max) ** 2 * (1.0 + rel_band), int(exclude_ii), int(cap),
+                                 _p(idx), _p(r2), _p(counts), int(bins), float(r_min),
+                                 float(r_max), rel_band, _p(lo), _p(hi), _p(n_amb))
+    if rc != 0:
+        raise ValueError(f"a row holds more than cap={cap} neighbours")
+    return counts, idx, r2, lo, hi, n_amb
 
 
 def _complex_pairs(v, n):

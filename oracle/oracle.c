@@ -168,6 +168,23 @@ static int64_t bin_of(double x, double r_min, double dr, int64_t bins)
  * lo <= counts <= hi.  Pinned by: brute-force numpy binning on tiny inputs,
  * FCC shell multiplicities, and the ideal-gas limit g -> (N-1)/N.
  * ---------------------------------------------------------------------- */
+/* One pair's contribution to the RDF bounds: the bins its squared distance
+ * x can reach within the band; a single bin counts in lo and hi, a range is
+ * ambiguous and counts in hi only (and in *amb). */
+static void rdf_add_pair(double x, double r_min, double dr, int64_t bins, double rel_band,
+                         uint64_t* tlo, uint64_t* thi, uint64_t* amb)
+{
+    const int64_t blo = bin_of(x / (1.0 + rel_band), r_min, dr, bins);
+    const int64_t bhi = bin_of(x / (1.0 - rel_band), r_min, dr, bins);
+    if (blo == bhi) {
+        if (blo >= 0 && blo < bins) { tlo[blo]++; thi[blo]++; }
+    } else {
+        ++*amb;
+        for (int64_t k = blo; k <= bhi; ++k)
+            if (k >= 0 && k < bins) thi[k]++;
+    }
+}
+
 int orc_rdf(const orc_box* b, const float* pts, int64_t n, const float* q, int64_t nq,
             int64_t bins, double r_min, double r_max, int32_t exclude_ii, double rel_band,
             uint64_t* lo, uint64_t* hi, uint64_t* n_amb)
@@ -189,16 +206,7 @@ int orc_rdf(const orc_box* b, const float* pts, int64_t n, const float* q, int64
                 if (exclude_ii && i == j) continue;
                 double x = pair_r2(b, pts + 3 * j, q + 3 * i, d);
                 if (x >= r2_lim) continue;
-                /* bins reachable within the band around x */
-                int64_t blo = bin_of(x / (1.0 + rel_band), r_min, dr, bins);
-                int64_t bhi = bin_of(x / (1.0 - rel_band), r_min, dr, bins);
-                if (blo == bhi) {
-                    if (blo >= 0 && blo < bins) { tlo[blo]++; thi[blo]++; }
-                } else {
-                    ++tamb;
-                    for (int64_t k = blo; k <= bhi; ++k)
-                        if (k >= 0 && k < bins) thi[k]++;
-                }
+                rdf_add_pair(x, r_min, dr, bins, rel_band, tlo, thi, &tamb);
             }
         }
 #pragma omp critical
@@ -211,6 +219,68 @@ int orc_rdf(const orc_box* b, const float* pts, int64_t n, const float* q, int64
     }
     *n_amb = amb_total;
     return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * The ball query and the RDF bounds of the same pairs in one sweep over all
+ * (query, point) pairs: the two definitions above evaluated together, so a
+ * large system is checked with one brute-force pass instead of three.
+ * Query row i is q[i] with global index q_first + i (exclude_ii drops
+ * j == q_first + i).  The row's points with r^2 < r2_limit go, in ascending
+ * j with their r^2, to idx / r2_out at i * cap onwards; counts[i] is the full
+ * row length, and a row longer than cap is cut there and makes the return
+ * value 1.  Every pair with r^2 < r_max^2 (1 + rel_band) is binned exactly as
+ * orc_rdf bins it into lo / hi and n_amb, which accumulate (the caller
+ * zeroes them), so row ranges can be swept one after another.  Pinned by:
+ * equality with orc_ball_count / orc_ball_fill and orc_rdf.
+ * ---------------------------------------------------------------------- */
+int orc_ball_rdf_rows(const orc_box* b, const float* pts, int64_t n, const float* q, int64_t nq,
+                      int64_t q_first, double r2_limit, int32_t exclude_ii, int64_t cap,
+                      int32_t* idx, double* r2_out, int64_t* counts, int64_t bins, double r_min,
+                      double r_max, double rel_band, uint64_t* lo, uint64_t* hi, uint64_t* n_amb)
+{
+    const double dr = (r_max - r_min) / (double)bins;
+    const double r2_hist = r_max * r_max * (1.0 + rel_band);
+    int cut = 0;
+    uint64_t amb_total = 0;
+#pragma omp parallel
+    {
+        uint64_t* tlo = (uint64_t*)calloc((size_t)bins, sizeof(uint64_t));
+        uint64_t* thi = (uint64_t*)calloc((size_t)bins, sizeof(uint64_t));
+        uint64_t tamb = 0;
+        int tcut = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nq; ++i) {
+            const int64_t self = q_first + i;
+            int64_t c = 0;
+            double d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                if (exclude_ii && j == self) continue;
+                const double x = pair_r2(b, pts + 3 * j, q + 3 * i, d);
+                if (x < r2_limit) {
+                    if (c < cap) {
+                        idx[i * cap + c] = (int32_t)j;
+                        r2_out[i * cap + c] = x;
+                    } else {
+                        tcut = 1;
+                    }
+                    ++c;
+                }
+                if (x < r2_hist) rdf_add_pair(x, r_min, dr, bins, rel_band, tlo, thi, &tamb);
+            }
+            counts[i] = c;
+        }
+#pragma omp critical
+        {
+            for (int64_t k = 0; k < bins; ++k) { lo[k] += tlo[k]; hi[k] += thi[k]; }
+            amb_total += tamb;
+            cut |= tcut;
+        }
+        free(tlo);
+        free(thi);
+    }
+    *n_amb += amb_total;
+    return cut;
 }
 
 /* ------------------------------------------------------------------------

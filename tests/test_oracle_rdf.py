@@ -112,3 +112,47 @@ def test_rdf_ambiguity_band_catches_edge_pair(orc):
     assert amb == 2
     assert lo.sum() == 0
     assert hi[2] == 2 and hi[3] == 2
+
+
+def test_one_sweep_ball_rdf_rows_equal_the_separate_definitions(orc):
+    """The one-sweep ball + RDF routine (used to write the full-size expected
+    values) equals the ball query and the RDF computed separately, also
+    when the rows are swept in pieces; and the numpy brute force pins the
+    rows through image search."""
+    rng = np.random.default_rng(5150)
+    for trial in range(4):
+        L = tuple(rng.uniform(6, 9, 3))
+        tilt = tuple(rng.uniform(-0.45, 0.45, 3))
+        n = 300
+        s = rng.uniform(-0.5, 0.5, (n, 3))
+        pts = (s @ workloads.lattice_vectors(L, tilt, 3).T).astype(np.float32)
+        half = 0.5 * brute.perpendicular_widths(L, tilt, 3).min()
+        r_max = 0.95 * half
+        box = orc.make_box(L, tilt, 3)
+        off, idx, r2 = orc.ball_query(box, pts, r_max)
+        lo_ref, hi_ref, amb_ref = orc.rdf_counts(box, pts, 23, r_max)
+        lo = np.zeros(23, np.uint64)
+        hi = np.zeros(23, np.uint64)
+        amb = np.zeros(1, np.uint64)
+        cuts = [0, 77, 78, 211, n]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            cnt, ri, rr, lo, hi, amb = orc.ball_rdf_rows(box, pts, r_max, 23, rows=(a, b), cap=128,
+                                                         lo=lo, hi=hi, n_amb=amb)
+            for t, q in enumerate(range(a, b)):
+                c = int(cnt[t])
+                assert c == off[q + 1] - off[q]
+                assert np.array_equal(ri[t, :c], idx[off[q]:off[q + 1]])
+                assert np.array_equal(rr[t, :c], r2[off[q]:off[q + 1]])
+                assert np.all(ri[t, c:] == -1)
+        assert np.array_equal(lo, lo_ref) and np.array_equal(hi, hi_ref)
+        assert int(amb[0]) == amb_ref
+        # rows against the image-search brute force
+        v = brute.pair_vectors(pts, L, tilt, 3)
+        R2 = (v.astype(np.float64) ** 2).sum(-1)
+        np.fill_diagonal(R2, np.inf)
+        for q in range(0, n, 37):
+            ref = np.nonzero(R2[q] < r_max ** 2 * (1 - 1e-5))[0]
+            assert set(ref.tolist()) <= set(idx[off[q]:off[q + 1]].tolist())
+    # a row longer than cap is reported
+    with pytest.raises(ValueError):
+        orc.ball_rdf_rows(box, pts, r_max, 23, cap=2)
