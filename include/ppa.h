@@ -306,7 +306,7 @@ int ppa_correlation_workspace_bytes(const ppa_box* box, int64_t n, int64_t nq, i
  * b = floor((r - r_min) / dr), dr = (r_max - r_min) / bins:
  *     sums[2b] + i sums[2b + 1] += conj(f_i) g_j,   counts[b] += 1,
  * where g_j = values[j] and f_i = qvalues[i] are complex.  The correlation
- * is C_b = (sums[2b] + i sums[2b + 1]) / counts[b] (host side).  Each term
+ * is C_b = (sums[2b] + i sums[2b + 1]) / counts[b] (ppa_correlation_finalize).  Each term
  * is formed in float64 from the float32 values (exact products, one
  * rounding); bins' sums are float64, accumulated per workgroup in LDS and
  * then summed in a fixed order.
@@ -420,6 +420,72 @@ int ppa_smooth_rdf_bwd(const ppa_box* box, const float* pts, int64_t n, int32_t 
  * of the two).  Queries the current device, no device work. */
 int ppa_smooth_rdf_workspace_bytes(const ppa_box* box, int64_t n, int32_t bins, float r_max,
                                    float sigma, size_t* bytes);
+
+/* ---- Normalisation of accumulated histograms (float64, device) ------------
+ * The paper reads the RDF as g(r) = exp(-beta F(r)), the potential of mean
+ * force in units of kT, and defines the PMFT as minus the logarithm of the
+ * histogram of neighbour positions in each particle's own frame ("PMFT");
+ * histograms accumulate over frames before they are averaged
+ * ("Implementation", reset=False).  These calls divide each bin by the count
+ * an ideal gas of the same density would give it, summed over the frames:
+ *     D = sum_f N_q,f * N_p,f / V_f   (V: volume in 3D, area Lx Ly in 2D),
+ * from per-frame host arrays boxes[n_frames], n_points[n_frames] (N_p, the
+ * points searched) and n_query[n_frames] (N_q, the query points; equal to
+ * N_p for a self-query).  D is formed on the host in float64 (PPA_EINVAL
+ * when it is 0, or a count is negative; PPA_EBOX for a bad box); one kernel
+ * on `stream` then writes every bin in float64.  Outputs are device arrays
+ * owned by the caller, overwritten (not accumulated).  -ln of an empty bin
+ * is +inf.  The additive constant of the PMF and PMFT (the paper defines them
+ * up to a constant) is fixed by this normalisation: an ideal gas gives
+ * g = pcf = 1 up to the (N-1)/N of a self-query. */
+
+/* RDF: g[b] = counts[b] / (D dV_b), dV_b the volume of the shell between the
+ * bin's edges e_b = r_min + b (r_max - r_min) / bins (4/3 pi (e1^3 - e0^3) in
+ * 3D, pi (e1^2 - e0^2) in 2D; the dimension is boxes[0].dim and every frame
+ * must share it); pmf[b] = -ln g[b] when pmf is non-NULL.
+ *   counts [bins] uint64 device; g [bins] float64 device; pmf [bins] float64
+ *   device or NULL. */
+int ppa_rdf_normalize(const uint64_t* counts, int32_t bins, double r_min, double r_max,
+                      int32_t n_frames, const ppa_box* boxes, const int64_t* n_points,
+                      const int64_t* n_query, double* g, double* pmf, hipStream_t stream);
+
+/* The RDF's per-bin factor alone: scale[b] = 1 / (D dV_b), so g = h * scale
+ * for any numerator h (the smoothed RDF's float64 h, whose gradient then
+ * passes through the same factor).  scale [bins] float64 device. */
+int ppa_rdf_bin_scale(int32_t bins, double r_min, double r_max, int32_t n_frames,
+                      const ppa_box* boxes, const int64_t* n_points, const int64_t* n_query,
+                      double* scale, hipStream_t stream);
+
+/* 2D PMFT (ppa_pmft2d counts [nbx][nby], bins of dx = 2 x_max / nbx by
+ * dy = 2 y_max / nby): pcf = counts / (D dx dy), pmft = -ln pcf (NULL to
+ * skip).  2D boxes only.  counts uint32 device; pcf, pmft float64 device. */
+int ppa_pmft2d_normalize(const uint32_t* counts, int32_t nbx, int32_t nby, double x_max,
+                         double y_max, int32_t n_frames, const ppa_box* boxes,
+                         const int64_t* n_points, const int64_t* n_query, double* pcf,
+                         double* pmft, hipStream_t stream);
+
+/* PMFT XYT (ppa_pmft_xyt counts [nbx][nby][nbt]): the orientation bin is
+ * weighted by its share 1 / nbt of the full turn, pcf = counts /
+ * (D dx dy / nbt), so an ideal gas gives 1.  2D boxes only. */
+int ppa_pmft_xyt_normalize(const uint32_t* counts, int32_t nbx, int32_t nby, int32_t nbt,
+                           double x_max, double y_max, int32_t n_frames, const ppa_box* boxes,
+                           const int64_t* n_points, const int64_t* n_query, double* pcf,
+                           double* pmft, hipStream_t stream);
+
+/* PMFT XYZ (ppa_pmft_xyz counts [nbx][nby][nbz]): pcf = counts /
+ * (D dx dy dz), dz = 2 z_max / nbz.  3D boxes only. */
+int ppa_pmft_xyz_normalize(const uint32_t* counts, int32_t nbx, int32_t nby, int32_t nbz,
+                           double x_max, double y_max, double z_max, int32_t n_frames,
+                           const ppa_box* boxes, const int64_t* n_points, const int64_t* n_query,
+                           double* pcf, double* pmft, hipStream_t stream);
+
+/* Correlation function from ppa_correlation's accumulated sums and counts
+ * (the density module's correlation of arbitrary quantities, "Analysis
+ * Modules"): corr[2b] + i corr[2b+1] = (sums[2b] + i sums[2b+1]) / counts[b],
+ * 0 for an empty bin.  sums, corr [bins x 2] float64 device; counts [bins]
+ * uint64 device. */
+int ppa_correlation_finalize(const double* sums, const uint64_t* counts, int32_t bins,
+                             double* corr, hipStream_t stream);
 
 /* ---- Batched analysis (an extension beyond the paper) --------------------
  * Many frames (a trajectory, or many systems of uneven size each with its

@@ -144,6 +144,16 @@ def lib():
             "ppa_batch_graph_destroy": [P],
             "ppa_smooth_rdf_fwd": [BP, P, i64, i32, f32, f32, i32, P, sz, P, P],
             "ppa_smooth_rdf_bwd": [BP, P, i64, i32, f32, f32, P, i32, P, sz, P, P],
+            "ppa_rdf_normalize": [P, i32, ctypes.c_double, ctypes.c_double, i32, BP, P, P, P, P,
+                                  P],
+            "ppa_rdf_bin_scale": [i32, ctypes.c_double, ctypes.c_double, i32, BP, P, P, P, P],
+            "ppa_pmft2d_normalize": [P, i32, i32, ctypes.c_double, ctypes.c_double, i32, BP, P, P,
+                                     P, P, P],
+            "ppa_pmft_xyt_normalize": [P, i32, i32, i32, ctypes.c_double, ctypes.c_double, i32, BP,
+                                       P, P, P, P, P],
+            "ppa_pmft_xyz_normalize": [P, i32, i32, i32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, i32, BP, P, P, P, P, P],
+            "ppa_correlation_finalize": [P, P, i32, P, P],
             "ppa_sync_status": [P, P],
             "ppa_profile_next": [P, P, P, P],
             "ppa_probe_lds_atomics": [i32, i32, i32, P, P],
@@ -431,16 +441,34 @@ def pmft2d_counts(box: Box, points, angles, nbx, nby, x_max, y_max, r_max, query
     return counts
 
 
-def normalize_pmft2d(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
-    """(pair correlation, PMFT) from 2D PMFT counts, float64 on the host:
-    pcf = counts / (n_frames N_q rho dx dy) with rho = N_p / area, and
-    PMFT = -ln(pcf) (+inf where a bin is empty)."""
-    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
-    nbx, nby = c.shape
-    dxdy = (2.0 * x_max / nbx) * (2.0 * y_max / nby)
-    pcf = c / (n_frames * n_query * (n_points / area) * dxdy)
-    with np.errstate(divide="ignore"):
-        pmft = -np.log(pcf)
+def _frames(boxes, n_points, n_query):
+    """Per-frame host arrays for the normalisation calls: (n_frames, CBox
+    array, int64 n_points, int64 n_query); scalars apply to every frame."""
+    boxes = [boxes] if isinstance(boxes, Box) else list(boxes)
+    F = len(boxes)
+    npt = np.broadcast_to(np.asarray(n_points, np.int64), (F,)).copy()
+    nq = np.broadcast_to(np.asarray(n_query, np.int64), (F,)).copy()
+    return F, (CBox * F)(*[b.c() for b in boxes]), npt, nq
+
+
+def _norm_outputs(counts, shape, with_log):
+    torch = _torch()
+    ratio = torch.empty(shape, dtype=torch.float64, device=counts.device)
+    neglog = torch.empty(shape, dtype=torch.float64, device=counts.device) if with_log else None
+    return ratio, neglog
+
+
+def normalize_pmft2d(counts, boxes, n_points, n_query, x_max, y_max, stream=None):
+    """(pair correlation, PMFT) float64 device tensors [nbx, nby] from 2D PMFT
+    counts accumulated over the frames of `boxes` (a Box or one per frame;
+    n_points / n_query per frame or scalars), by ppa_pmft2d_normalize."""
+    F, cb, npt, nq = _frames(boxes, n_points, n_query)
+    nbx, nby = counts.shape
+    pcf, pmft = _norm_outputs(counts, (nbx, nby), True)
+    _check(lib().ppa_pmft2d_normalize(_ptr(counts.contiguous()), int(nbx), int(nby), float(x_max),
+                                      float(y_max), F, cb, npt.ctypes.data_as(ctypes.c_void_p),
+                                      nq.ctypes.data_as(ctypes.c_void_p), _ptr(pcf), _ptr(pmft),
+                                      _stream(stream)))
     return pcf, pmft
 
 
@@ -498,16 +526,17 @@ def pmft_xyt_counts(box: Box, points, angles, nbx, nby, nbt, x_max, y_max, r_max
     return counts
 
 
-def normalize_pmft_xyt(counts, n_points, n_query, area, x_max, y_max, n_frames=1):
-    """(pair correlation, PMFT) from XYT counts, float64 on the host:
-    pcf = counts / (n_frames N_q rho dx dy (dt / 2 pi)) with rho = N_p / area,
-    so an ideal gas gives 1; PMFT = -ln(pcf) (+inf where a bin is empty)."""
-    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
-    nbx, nby, nbt = c.shape
-    w = (2.0 * x_max / nbx) * (2.0 * y_max / nby) / nbt
-    pcf = c / (n_frames * n_query * (n_points / area) * w)
-    with np.errstate(divide="ignore"):
-        pmft = -np.log(pcf)
+def normalize_pmft_xyt(counts, boxes, n_points, n_query, x_max, y_max, stream=None):
+    """(pcf, PMFT) float64 device tensors [nbx, nby, nbt] from XYT counts by
+    ppa_pmft_xyt_normalize (the angle bin weighted by its share of a turn)."""
+    F, cb, npt, nq = _frames(boxes, n_points, n_query)
+    nbx, nby, nbt = counts.shape
+    pcf, pmft = _norm_outputs(counts, (nbx, nby, nbt), True)
+    _check(lib().ppa_pmft_xyt_normalize(_ptr(counts.contiguous()), int(nbx), int(nby), int(nbt),
+                                        float(x_max), float(y_max), F, cb,
+                                        npt.ctypes.data_as(ctypes.c_void_p),
+                                        nq.ctypes.data_as(ctypes.c_void_p), _ptr(pcf), _ptr(pmft),
+                                        _stream(stream)))
     return pcf, pmft
 
 
@@ -551,16 +580,17 @@ def pmft_xyz_counts(box: Box, points, quats, nbx, nby, nbz, x_max, y_max, z_max,
     return counts
 
 
-def normalize_pmft_xyz(counts, n_points, n_query, volume, x_max, y_max, z_max, n_frames=1):
-    """(pair correlation, PMFT) from XYZ counts, float64 on the host:
-    pcf = counts / (n_frames N_q rho dx dy dz), rho = N_p / volume;
-    PMFT = -ln(pcf) (+inf where a bin is empty)."""
-    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts).astype(np.float64)
-    nbx, nby, nbz = c.shape
-    w = (2.0 * x_max / nbx) * (2.0 * y_max / nby) * (2.0 * z_max / nbz)
-    pcf = c / (n_frames * n_query * (n_points / volume) * w)
-    with np.errstate(divide="ignore"):
-        pmft = -np.log(pcf)
+def normalize_pmft_xyz(counts, boxes, n_points, n_query, x_max, y_max, z_max, stream=None):
+    """(pcf, PMFT) float64 device tensors [nbx, nby, nbz] from XYZ counts by
+    ppa_pmft_xyz_normalize."""
+    F, cb, npt, nq = _frames(boxes, n_points, n_query)
+    nbx, nby, nbz = counts.shape
+    pcf, pmft = _norm_outputs(counts, (nbx, nby, nbz), True)
+    _check(lib().ppa_pmft_xyz_normalize(_ptr(counts.contiguous()), int(nbx), int(nby), int(nbz),
+                                        float(x_max), float(y_max), float(z_max), F, cb,
+                                        npt.ctypes.data_as(ctypes.c_void_p),
+                                        nq.ctypes.data_as(ctypes.c_void_p), _ptr(pcf), _ptr(pmft),
+                                        _stream(stream)))
     return pcf, pmft
 
 
@@ -629,14 +659,15 @@ def correlation_sums(box: Box, points, values, bins, r_max, r_min=0.0, query_poi
     return sums, counts
 
 
-def correlation(box: Box, points, values, bins, r_max, r_min=0.0, **kw):
-    """C(r) per bin (complex128, host; 0 where a bin holds no pair) and the counts."""
-    sums, counts = correlation_sums(box, points, values, bins, r_max, r_min, **kw)
-    s = sums.cpu().numpy()
-    c = counts.cpu().numpy().astype(np.float64)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        C = np.where(c > 0, (s[:, 0] + 1j * s[:, 1]) / np.maximum(c, 1), 0)
-    return C, counts
+def correlation(box: Box, points, values, bins, r_max, r_min=0.0, stream=None, **kw):
+    """C(r) per bin (float64 device tensor [bins, 2] of (re, im), 0 where a bin
+    holds no pair; ppa_correlation_finalize) and the pair counts."""
+    torch = _torch()
+    sums, counts = correlation_sums(box, points, values, bins, r_max, r_min, stream=stream, **kw)
+    corr = torch.empty_like(sums)
+    _check(lib().ppa_correlation_finalize(_ptr(sums), _ptr(counts), int(bins), _ptr(corr),
+                                          _stream(stream)))
+    return corr, counts
 
 
 def steinhardt(box: Box, points, neighbors, l, query_points=None, with_w=False, ws=None,
@@ -830,16 +861,11 @@ def smooth_rdf(points, box: Box, bins, r_max, sigma):
     return _SmoothRDF.apply(points, box, bins, r_max, sigma)
 
 
-def smooth_rdf_g(h, n_points, volume, r_max, dim=3):
-    """g_b = h_b / (N rho dV_b) on the bins of [0, r_max) (differentiable in h)."""
-    torch = _torch()
-    bins = h.shape[-1]
-    e = np.arange(bins + 1, dtype=np.float64) * (float(r_max) / bins)
-    dv = (4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)) if dim == 3 else \
-        math.pi * (e[1:] ** 2 - e[:-1] ** 2)
-    scale = torch.as_tensor(1.0 / (n_points * (n_points / volume) * dv), dtype=h.dtype,
-                            device=h.device)
-    return h * scale
+def smooth_rdf_g(h, box: Box, n_points, r_max, stream=None):
+    """g_b = h_b * scale_b on the bins of [0, r_max), scale from
+    ppa_rdf_bin_scale (differentiable in h)."""
+    scale = rdf_bin_scale(h.shape[-1], box, n_points, n_points, 0.0, r_max, stream=stream)
+    return h * scale.to(h.dtype)
 
 
 class BatchPlan:
@@ -963,13 +989,31 @@ def rdf_from_nlist(nl: NeighborList, bins, r_max, r_min=0.0, counts=None, stream
     return counts
 
 
-def normalize_rdf(counts, n_points, n_query, volume, r_min, r_max, dim=3, n_frames=1):
-    """g_b = h_b / (N_q rho dV_b) with rho = N_p / V (float64, host)."""
-    c = np.asarray(counts.cpu() if hasattr(counts, "cpu") else counts, dtype=np.float64)
-    B = c.shape[-1]
-    e = r_min + np.arange(B + 1, dtype=np.float64) * ((r_max - r_min) / B)
-    dv = (4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)) if dim == 3 else math.pi * (e[1:] ** 2 - e[:-1] ** 2)
-    return c / (n_frames * n_query * (n_points / volume) * dv)
+def normalize_rdf(counts, boxes, n_points, n_query, r_min, r_max, stream=None):
+    """(g, PMF = -ln g) float64 device tensors from RDF counts accumulated over
+    the frames of `boxes` (a Box or one per frame; n_points / n_query per
+    frame or scalars), by ppa_rdf_normalize."""
+    F, cb, npt, nq = _frames(boxes, n_points, n_query)
+    bins = counts.shape[-1]
+    g, pmf = _norm_outputs(counts, (bins,), True)
+    _check(lib().ppa_rdf_normalize(_ptr(counts.contiguous()), int(bins), float(r_min),
+                                   float(r_max), F, cb, npt.ctypes.data_as(ctypes.c_void_p),
+                                   nq.ctypes.data_as(ctypes.c_void_p), _ptr(g), _ptr(pmf),
+                                   _stream(stream)))
+    return g, pmf
+
+
+def rdf_bin_scale(bins, boxes, n_points, n_query, r_min, r_max, stream=None):
+    """The RDF's per-bin factor 1 / (D dV_b) (float64 device tensor [bins]),
+    by ppa_rdf_bin_scale."""
+    torch = _torch()
+    F, cb, npt, nq = _frames(boxes, n_points, n_query)
+    scale = torch.empty(int(bins), dtype=torch.float64, device="cuda")
+    _check(lib().ppa_rdf_bin_scale(int(bins), float(r_min), float(r_max), F, cb,
+                                   npt.ctypes.data_as(ctypes.c_void_p),
+                                   nq.ctypes.data_as(ctypes.c_void_p), _ptr(scale),
+                                   _stream(stream)))
+    return scale
 
 
 def version():

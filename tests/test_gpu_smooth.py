@@ -124,7 +124,7 @@ def test_autograd_function(ppa):
     t = torch.as_tensor(oracle.smooth_rdf_g(oracle.smooth_rdf_h(_obox(tgt), tgt.points, BINS, R_MAX,
                                                                 SIGMA), n, V, R_MAX)).cuda()
     p = torch.as_tensor(s.points).cuda().requires_grad_(True)
-    g = ppa.smooth_rdf_g(ppa.smooth_rdf(p, box, BINS, R_MAX, SIGMA), n, V, R_MAX)
+    g = ppa.smooth_rdf_g(ppa.smooth_rdf(p, box, BINS, R_MAX, SIGMA), box, n, R_MAX)
     loss = ((g - t) ** 2).sum()
     loss.backward()
     h_ref = oracle.smooth_rdf_h(_obox(s), s.points, BINS, R_MAX, SIGMA)

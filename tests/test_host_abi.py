@@ -185,24 +185,56 @@ def test_knn_workspace_and_argument_errors():
     assert call(ws_bytes=64) == ppa.PPA_EWORKSPACE
 
 
-def test_normalisations_match_the_oracle_closed_forms():
-    """The binding's host-side normalisations against the oracle's."""
-    import oracle
-    rng = np.random.default_rng(2)
-    c = rng.integers(0, 1000, 64)
-    g = ppa.normalize_rdf(c, 5000, 4000, 1234.5, 0.5, 3.0, dim=3, n_frames=3)
-    np.testing.assert_allclose(g, oracle.rdf_normalize(c, 5000, 4000, 1234.5, 0.5, 3.0, 3, 3),
-                               rtol=1e-13)
-    g2 = ppa.normalize_rdf(c, 5000, 5000, 99.0, 0.0, 2.0, dim=2)
-    np.testing.assert_allclose(g2, oracle.rdf_normalize(c, 5000, 5000, 99.0, 0.0, 2.0, 2),
-                               rtol=1e-13)
-    cc = rng.integers(0, 50, (20, 30))
-    cc[3, 4] = 0
-    pcf, pmft = ppa.normalize_pmft2d(cc, 1000, 800, 345.0, 2.0, 3.0, n_frames=2)
-    ref = oracle.pmft2d_from_counts(cc, 1000, 800, 345.0, 2.0, 3.0, 2)
-    assert np.isinf(pmft[3, 4]) and np.isinf(ref[3, 4])
-    fin = np.isfinite(ref)
-    np.testing.assert_allclose(pmft[fin], ref[fin], rtol=1e-12, atol=1e-12)
+def test_normalisation_host_checks():
+    """The normalisation calls validate their host arguments before any
+    device work (the device pointers here are never dereferenced)."""
+    L = ppa.lib()
+    dev = ctypes.c_void_p(4096)
+    b3 = ppa.Box.cube(10.0)
+    b2 = ppa.Box((10.0, 10.0, 1.0), (0.0, 0.0, 0.0), 2)
+
+    def frames(boxes, npt, nq):
+        F = len(boxes)
+        cb = (ppa.CBox * F)(*[b.c() for b in boxes])
+        a = np.asarray(npt, np.int64)
+        q = np.asarray(nq, np.int64)
+        return F, cb, a, q
+
+    def rdf(bins=10, r_min=0.0, r_max=2.0, boxes=(b3,), npt=(100,), nq=(100,), counts=dev, g=dev,
+            n_frames=None):
+        F, cb, a, q = frames(boxes, npt, nq)
+        return L.ppa_rdf_normalize(counts, bins, r_min, r_max, F if n_frames is None else n_frames,
+                                   cb, a.ctypes.data_as(ctypes.c_void_p),
+                                   q.ctypes.data_as(ctypes.c_void_p), g, None, None)
+    assert rdf(bins=0) == ppa.PPA_EINVAL
+    assert rdf(r_min=2.0) == ppa.PPA_EINVAL
+    assert rdf(r_max=float("nan")) == ppa.PPA_EINVAL
+    assert rdf(counts=None) == ppa.PPA_EINVAL
+    assert rdf(g=None) == ppa.PPA_EINVAL
+    assert rdf(n_frames=0) == ppa.PPA_EINVAL
+    assert rdf(npt=(0,)) == ppa.PPA_EINVAL          # no ideal-gas pairs to divide by
+    assert rdf(nq=(-1,)) == ppa.PPA_EINVAL
+    assert rdf(boxes=(b3, b2), npt=(5, 5), nq=(5, 5)) == ppa.PPA_EINVAL  # mixed dimensions
+    assert rdf(boxes=(ppa.Box((10.0, -1.0, 10.0)),)) == ppa.PPA_EBOX
+
+    def pmft2(nbx=10, nby=10, x=2.0, y=2.0, boxes=(b2,)):
+        F, cb, a, q = frames(boxes, (100,), (100,))
+        return L.ppa_pmft2d_normalize(dev, nbx, nby, x, y, F, cb, a.ctypes.data_as(ctypes.c_void_p),
+                                      q.ctypes.data_as(ctypes.c_void_p), dev, None, None)
+    assert pmft2(nbx=0) == ppa.PPA_EINVAL
+    assert pmft2(y=0.0) == ppa.PPA_EINVAL
+    assert pmft2(boxes=(b3,)) == ppa.PPA_EINVAL       # 2D only
+    F, cb, a, q = frames((b2,), (100,), (100,))
+    assert L.ppa_pmft_xyz_normalize(dev, 5, 5, 5, 1.0, 1.0, 1.0, F, cb,
+                                    a.ctypes.data_as(ctypes.c_void_p),
+                                    q.ctypes.data_as(ctypes.c_void_p), dev, None,
+                                    None) == ppa.PPA_EINVAL  # 3D only
+    assert L.ppa_pmft_xyt_normalize(dev, 5, 5, 0, 1.0, 1.0, F, cb,
+                                    a.ctypes.data_as(ctypes.c_void_p),
+                                    q.ctypes.data_as(ctypes.c_void_p), dev, None,
+                                    None) == ppa.PPA_EINVAL
+    assert L.ppa_correlation_finalize(dev, None, 10, dev, None) == ppa.PPA_EINVAL
+    assert L.ppa_correlation_finalize(dev, dev, 0, dev, None) == ppa.PPA_EINVAL
 
 
 def test_pmft_workspace_and_errors():
