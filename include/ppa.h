@@ -134,6 +134,24 @@ int ppa_rdf(const ppa_box* box, const float* pts, int64_t n, const float* qpts, 
             int32_t* point_idx, float* dist, int64_t capacity, int64_t* n_pairs_dev,
             hipStream_t stream);
 
+/* ppa_rdf for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same call without a workspace argument.  Its scratch is a static device
+ * array of the library, 64 MiB per device, held from the first call on a
+ * device until the process ends; the call allocates nothing and calls no
+ * allocating routine.  Arguments, outputs and results are those of ppa_rdf.
+ * A call whose workspace (ppa_workspace_bytes with PPA_WS_NLIST when
+ * offsets is non-NULL) would exceed 64 MiB returns PPA_EWORKSPACE before
+ * any device work (about 1.4 million points for the self-query ball list).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller.  The device status of the last call is read with
+ * ppa_sync_status(NULL, stream) on the same device. */
+int ppa_rdf_static(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags,
+                   uint64_t* counts_hist, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                   float* dist, int64_t capacity, int64_t* n_pairs_dev, hipStream_t stream);
+
 /* RDF histogram from a stored NeighborList's distances (the paper's reuse of
  * a NeighborList across analyses, "Implementation").  dist [*n_pairs_dev]
  * float32 device, at most `capacity` are read; counts_hist accumulated. */
@@ -596,7 +614,8 @@ int ppa_probe_global_atomics(int32_t log2_words, int32_t iters, int32_t blocks,
                              uint32_t* hist_dev, hipStream_t stream);
 
 /* Waits for the stream and returns the device status of the last call that
- * used this workspace (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE, for a
+ * used this workspace (ws NULL: the static scratch of ppa_rdf_static on the
+ * current device, PPA_EINVAL if no such call was made there) (PPA_OK, PPA_ECAPACITY, PPA_ENONFINITE, for a
  * k-nearest query PPA_ERANGE, and for ppa_steinhardt / ppa_cluster /
  * ppa_knn_from_nlist PPA_EINVAL when a NeighborList offset or index was out
  * of range, PPA_ERANGE for too many ties in ppa_knn_from_nlist). */

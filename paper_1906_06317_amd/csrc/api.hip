@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace ppa {
@@ -1005,6 +1007,62 @@ int ppa_query_ball(const ppa_box* box, const float* pts, int64_t n, const float*
     return run_pairs(c);
 }
 
+}  // extern "C"
+
+// Scratch of ppa_rdf_static: a fixed device array, so that call allocates
+// nothing.  Its address is looked up once per device (each device holds its
+// own copy of the array) and kept; host code uses only that address.
+namespace ppa {
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int static_scratch(void** out, bool create)
+{
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev), "get device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(PPA_EDEVICE, "device ordinal %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (!create) return set_error(PPA_EINVAL, "workspace is NULL");
+        void* p = nullptr;
+        rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "static scratch address");
+        if (rc) return rc;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PPA_OK;
+}
+}  // namespace
+}  // namespace ppa
+
+extern "C" {
+
+int ppa_rdf_static(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
+                   int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags,
+                   uint64_t* counts_hist, int64_t* offsets, int32_t* counts, int32_t* point_idx,
+                   float* dist, int64_t capacity, int64_t* n_pairs_dev, hipStream_t stream)
+{
+    size_t need = 0;
+    int rc = ppa_workspace_bytes(box, n, qpts ? nq : 0, r_max, offsets ? PPA_WS_NLIST : 0, &need);
+    if (rc) return rc;
+    if (need > kStaticScratchBytes)
+        return set_error(PPA_EWORKSPACE,
+                         "the call needs %zu bytes of scratch, more than the static %zu bytes; "
+                         "use ppa_rdf with a workspace",
+                         need, kStaticScratchBytes);
+    void* ws = nullptr;
+    if ((rc = static_scratch(&ws, true))) return rc;
+    QueryCall c{box,      pts,    n,        qpts,      nq,       r_max,       exclude_ii, flags,
+                ws,       kStaticScratchBytes, offsets != nullptr, offsets, counts, point_idx,
+                dist,     capacity, n_pairs_dev, true, bins, r_min, counts_hist, stream};
+    return run_pairs(c);
+}
+
 int ppa_rdf(const ppa_box* box, const float* pts, int64_t n, const float* qpts, int64_t nq,
             int32_t bins, float r_min, float r_max, int32_t exclude_ii, int32_t flags, void* ws,
             size_t ws_bytes, uint64_t* counts_hist, int64_t* offsets, int32_t* counts,
@@ -1375,8 +1433,13 @@ int ppa_smooth_rdf_bwd(const ppa_box* box, const float* pts, int64_t n, int32_t 
 
 int ppa_sync_status(const void* ws, hipStream_t stream)
 {
-    if (!ws) return set_error(PPA_EINVAL, "workspace is NULL");
-    int rc = hip_check(hipStreamSynchronize(stream), "stream synchronize");
+    int rc;
+    if (!ws) {  // the static scratch of ppa_rdf_static on the current device
+        void* p = nullptr;
+        if ((rc = static_scratch(&p, false))) return rc;
+        ws = p;
+    }
+    rc = hip_check(hipStreamSynchronize(stream), "stream synchronize");
     if (rc) return rc;
     unsigned st = 0;
     rc = hip_check(hipMemcpy(&st, ws, sizeof(st), hipMemcpyDeviceToHost), "read status");
