@@ -31,6 +31,14 @@ __device__ __forceinline__ float lane_off(float v, int t)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
 }
 
+// v with lane t replaced by the uniform value x (one v_writelane; the lane
+// select goes through M0, as the instruction reads at most one other SGPR).
+__device__ __forceinline__ int with_lane(int v, int t, int x)
+{
+    asm("v_writelane_b32 %0, %1, m0" : "=v"(v) : "s"(x), "{m0}"(t), "0"(v));
+    return v;
+}
+
 __device__ __forceinline__ long long lane_of64(long long v, int t)
 {
     const unsigned lo = (unsigned)lane_of((int)(unsigned)v, t);
@@ -279,6 +287,88 @@ struct Slots {
         }
         return dist2<DIM>(x[s] - q.x, y[s] - q.y, z[s] - q.z) < r2max;
     }
+};
+
+// The candidates of one home cell in NS register slots, held for the
+// expanded in/out test: -2c and |c|^2 per candidate, so a test against a
+// query in scalar registers is three FMAs and a compare,
+//     t = |c|^2 + (-2c).q < r_max^2 - |q|^2.
+// (-2c).q is the same exact product as c.(-2q), so t equals the value the
+// test of Slots computes, bit for bit; c = -0.5 (-2c) is recovered exactly.
+// Entries past the end are far away, so they never hit.
+template <int DIM, int NS>
+struct DotSlots {
+    float mx[NS > 0 ? NS : 1], my[NS > 0 ? NS : 1], mz[NS > 0 ? NS : 1];
+    float cc[NS > 0 ? NS : 1];
+    int id[NS > 0 ? NS : 1];
+
+    __device__ __forceinline__ void load(const PairIn& in, int nsten, const StencilLds& S,
+                                         const float4* off, int k0, int C, int lane)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            float x = kFar, y = kFar, z = kFar;
+            id[s] = -1;
+            const int k = k0 + s * kWave + lane;
+            if (k < C) fetch<DIM>(in, nsten, S, off, k, x, y, z, id[s]);
+            cc[s] = dist2<DIM>(x, y, z);
+            mx[s] = -2.f * x;
+            my[s] = -2.f * y;
+            mz[s] = -2.f * z;
+        }
+    }
+    __device__ __forceinline__ bool hit(int s, float qx, float qy, float qz, float thr) const
+    {
+        float t = fmaf(mx[s], qx, cc[s]);
+        t = fmaf(my[s], qy, t);
+        if (DIM == 3) t = fmaf(mz[s], qz, t);
+        return t < thr;
+    }
+};
+
+// One query of a DotChunk.
+struct DQuery {
+    float x, y, z;
+    float thr;  // r_max^2 - |q|^2
+    int id;
+};
+
+// Query points of a tile, 64 at a time: each lane loads one and writes
+// (x, y, z, r_max^2 - |q|^2) to its wavefront's row of 64 float4 in LDS
+// (the expression the Query of QueryChunk holds).  A query is then read by
+// every lane with one broadcast LDS load, so its values arrive in vector
+// registers, the operands the tests read fastest, with no cross-lane VALU
+// work per query.
+struct DotChunk {
+    float4 q;  // this lane's query point (index bits in w)
+    int n;
+    float4* row;
+
+    template <int DIM>
+    __device__ __forceinline__ void load(const PairIn& in, int first, int count, int lane,
+                                         float r2max, float4* lds_row)
+    {
+        n = uniform(min(kWave, count));
+        q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < n) q = in.qs[first + lane];
+        const float z = DIM == 3 ? q.z : 0.f;
+        row = lds_row;
+        wave_sync();  // the previous chunk's reads are done
+        row[lane] = make_float4(q.x, q.y, z, r2max - dist2<DIM>(q.x, q.y, z));
+        wave_sync();
+    }
+    __device__ __forceinline__ DQuery get(int t) const
+    {
+        const float4 v = row[t];
+        DQuery r;
+        r.x = v.x;
+        r.y = v.y;
+        r.z = v.z;
+        r.thr = v.w;
+        r.id = lane_of(__float_as_int(q.w), t);
+        return r;
+    }
+    __device__ __forceinline__ int my_id() const { return __float_as_int(q.w); }
 };
 
 // Query points of a tile, 64 at a time, one per lane.

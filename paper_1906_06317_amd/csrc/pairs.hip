@@ -18,9 +18,13 @@
 // The in/out test of a candidate c against query q is either the plain
 // |c - q|^2 < r_max^2 or, when the host has bounded its rounding error well
 // inside the parity band, the expanded |c|^2 - 2 c.q < r_max^2 - |q|^2 (three
-// FMAs against the query's scalars).  Both passes evaluate the same
-// expression, so they agree pair by pair; every reported distance and bin is
-// recomputed from the difference c - q.
+// FMAs).  The count pass keeps -2c and |c|^2 in its slots and reads each
+// query, with its r_max^2 - |q|^2, from a per-wavefront LDS row by one
+// broadcast load, so the tests take all operands from vector registers; two
+// queries go at a time.  The fill pass keeps c and forms -2q per query; the
+// products (-2c).q and c.(-2q) are equal and exact inside the FMA, so both
+// passes evaluate the same value and agree pair by pair.  Every reported
+// distance and bin is recomputed from the difference c - q.
 // The NeighborList takes two passes so rows land in query order without
 // atomics: count_kernel writes row lengths, a scan turns them into CSR
 // offsets, and fill_kernel compacts hits with ballot + mbcnt into a small
@@ -48,24 +52,69 @@ constexpr int kMaxBatchLdsBins = 1024;  // per-wavefront histograms of a batch u
 // ---------------------------------------------------------------------------
 // Pass 1: row lengths.
 // ---------------------------------------------------------------------------
-// Hits of one query against NS slots (the query's own entry included).
-template <int DIM, int EXCL, int NS, bool DOT>
-__device__ __forceinline__ int count_hits(const Slots<DIM, NS>& c, const Query& q, float r2max)
+// Row lengths of the tile's queries, expanded test: candidates as -2c and
+// |c|^2, each query's coordinates and r_max^2 - |q|^2 read from its lane
+// (four readlanes), then three FMAs and a compare per slot.
+template <int DIM, int EXCL, int NS>
+__device__ __forceinline__ void count_tile_dot(const PairIn& in, const GeomView& G,
+                                               const StencilLds& S, const float4* off, int C,
+                                               int q0, int q1, int lane, float4* qrow,
+                                               int32_t* __restrict__ counts)
 {
-    int n = 0;
+    DotSlots<DIM, NS> c;
+    c.load(in, G.nsten, S, off, 0, C, lane);
+    for (int c0 = q0; c0 < q1; c0 += kWave) {
+        DotChunk Q;
+        Q.template load<DIM>(in, c0, q1 - c0, lane, G.r2max, qrow);
+        int cnt_v = 0;
+        // two queries at a time: two independent test chains interleave
+        int t = 0;
+        for (; t + 1 < Q.n; t += 2) {
+            const DQuery qa = Q.get(t);
+            const DQuery qb = Q.get(t + 1);
+            int na = 0, nb = 0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        bool h = c.template hit<DOT>(s, q, r2max);
-        if (EXCL == 2) h = h && c.id[s] != q.id;
-        n += __popcll(__ballot(h));
+            for (int s = 0; s < NS; ++s) {
+                bool ha = c.hit(s, qa.x, qa.y, qa.z, qa.thr);
+                bool hb = c.hit(s, qb.x, qb.y, qb.z, qb.thr);
+                if (EXCL == 2) {
+                    ha = ha && c.id[s] != qa.id;
+                    hb = hb && c.id[s] != qb.id;
+                }
+                na += __popcll(__ballot(ha));
+                nb += __popcll(__ballot(hb));
+            }
+            // a point querying itself always finds its own entry, at r = 0
+            if (EXCL == 1) {
+                na -= 1;
+                nb -= 1;
+            }
+            cnt_v = with_lane(cnt_v, t, na);
+            cnt_v = with_lane(cnt_v, t + 1, nb);
+        }
+        if (t < Q.n) {
+            const DQuery q = Q.get(t);
+            int n = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                bool h = c.hit(s, q.x, q.y, q.z, q.thr);
+                if (EXCL == 2) h = h && c.id[s] != q.id;
+                n += __popcll(__ballot(h));
+            }
+            if (EXCL == 1) n -= 1;
+            cnt_v = with_lane(cnt_v, t, n);
+        }
+        if (lane < Q.n) counts[Q.my_id()] = cnt_v;
     }
-    return n;
 }
 
+// The same with the plain test |c - q|^2 < r_max^2 (when the host could not
+// bound the expanded test's rounding inside the parity band).
 template <int DIM, int EXCL, int NS>
-__device__ __forceinline__ void count_tile(const PairIn& in, const GeomView& G,
-                                           const StencilLds& S, const float4* off, int C, int q0,
-                                           int q1, int lane, int32_t* __restrict__ counts)
+__device__ __forceinline__ void count_tile_plain(const PairIn& in, const GeomView& G,
+                                                 const StencilLds& S, const float4* off, int C,
+                                                 int q0, int q1, int lane,
+                                                 int32_t* __restrict__ counts)
 {
     Slots<DIM, NS> c;
     c.load(in, G.nsten, S, off, 0, C, lane);
@@ -76,11 +125,15 @@ __device__ __forceinline__ void count_tile(const PairIn& in, const GeomView& G,
         int cnt_v = 0;
         for (int t = 0; t < Q.n; ++t) {
             const Query q = Q.get<DIM>(t, r2max);
-            int n = G.dot ? count_hits<DIM, EXCL, NS, true>(c, q, r2max)
-                          : count_hits<DIM, EXCL, NS, false>(c, q, r2max);
-            // a point querying itself always finds its own entry, at r = 0
+            int n = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                bool h = c.template hit<false>(s, q, r2max);
+                if (EXCL == 2) h = h && c.id[s] != q.id;
+                n += __popcll(__ballot(h));
+            }
             if (EXCL == 1) n -= 1;
-            cnt_v = lane == t ? n : cnt_v;
+            cnt_v = with_lane(cnt_v, t, n);
         }
         if (lane < Q.n) counts[Q.my_id()] = cnt_v;
     }
@@ -104,13 +157,49 @@ __device__ __forceinline__ void count_chunked(const PairIn& in, const GeomView& 
             c.load(in, G.nsten, S, off, k0, C, lane);
             for (int t = 0; t < Q.n; ++t) {
                 const Query q = Q.get<DIM>(t, r2max);
-                const int n = G.dot ? count_hits<DIM, EXCL, kChunkSlots, true>(c, q, r2max)
-                                    : count_hits<DIM, EXCL, kChunkSlots, false>(c, q, r2max);
+                int n = 0;
+#pragma unroll
+                for (int s = 0; s < kChunkSlots; ++s) {
+                    bool h = G.dot ? c.template hit<true>(s, q, r2max)
+                                   : c.template hit<false>(s, q, r2max);
+                    if (EXCL == 2) h = h && c.id[s] != q.id;
+                    n += __popcll(__ballot(h));
+                }
                 cnt_v += lane == t ? n : 0;
             }
         }
         if (lane < Q.n) counts[Q.my_id()] = cnt_v;
     }
+}
+
+// Row lengths of one home cell: the slot count picks the unrolled code.
+template <int DIM, int EXCL>
+__device__ __forceinline__ void count_cell(const PairIn& in, const GeomView& V,
+                                           const StencilLds& S, const float4* off, int C, int q0,
+                                           int q1, int lane, float4* qrow,
+                                           int32_t* __restrict__ counts)
+{
+    const int ns = (C + kWave - 1) / kWave;
+    if (V.dot) {
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: count_tile_dot<DIM, EXCL, N>(in, V, S, off, C, q0, q1, lane, qrow, counts); return;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
+#undef PPA_CASE
+        default: break;
+        }
+    } else {
+        switch (ns) {
+#define PPA_CASE(N) \
+    case N: count_tile_plain<DIM, EXCL, N>(in, V, S, off, C, q0, q1, lane, counts); return;
+            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
+            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
+#undef PPA_CASE
+        default: break;
+        }
+    }
+    count_chunked<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, counts);
 }
 
 template <int DIM, int EXCL>
@@ -119,6 +208,7 @@ __global__ void __launch_bounds__(kBlock, 6) count_kernel(const PairIn in, const
 {
     __shared__ float4 s_off[27];
     __shared__ StencilLds s_st[kWavesPerBlock];
+    __shared__ float4 s_q[kWavesPerBlock][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     StencilLds& S = s_st[wv];
@@ -134,15 +224,7 @@ __global__ void __launch_bounds__(kBlock, 6) count_kernel(const PairIn in, const
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
         const int C = stencil<DIM>(in, V, tile, lane, S);
-        const int ns = (C + kWave - 1) / kWave;
-        switch (ns) {
-#define PPA_CASE(N) \
-    case N: count_tile<DIM, EXCL, N>(in, V, S, s_off, C, q0, q1, lane, counts); break;
-            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
-            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
-#undef PPA_CASE
-        default: count_chunked<DIM, EXCL>(in, V, S, s_off, C, q0, q1, lane, counts);
-        }
+        count_cell<DIM, EXCL>(in, V, S, s_off, C, q0, q1, lane, s_q[wv], counts);
     }
 }
 
@@ -597,6 +679,7 @@ __global__ void __launch_bounds__(kBlock, 5) count_batch_kernel(const PairIn in,
 {
     __shared__ float4 s_off[kWavesPerBlock][27];
     __shared__ StencilLds s_st[kWavesPerBlock];
+    __shared__ float4 s_q[kWavesPerBlock][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     StencilLds& S = s_st[wv];
@@ -616,15 +699,7 @@ __global__ void __launch_bounds__(kBlock, 5) count_batch_kernel(const PairIn in,
         const int q1 = in.q_start[tile + 1];
         if (q0 == q1) continue;
         const int C = stencil<DIM>(in, V, tile, lane, S);
-        const int ns = (C + kWave - 1) / kWave;
-        switch (ns) {
-#define PPA_CASE(N) \
-    case N: count_tile<DIM, EXCL, N>(in, V, S, off, C, q0, q1, lane, counts); break;
-            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
-            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10) PPA_CASE(11) PPA_CASE(12)
-#undef PPA_CASE
-        default: count_chunked<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, counts);
-        }
+        count_cell<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, s_q[wv], counts);
     }
 }
 
