@@ -6,7 +6,12 @@
 // and counted in a uniform 2D histogram on [-x_max, x_max) x [-y_max, y_max).
 //
 // The pairs come from the ball query's cell list, one wavefront per home
-// cell, candidates in register slots, each query in scalar registers.  The
+// cell, candidates in register slots, each query in scalar registers.  A
+// query finds about 20 bonds among a slot's 64 candidates, so binning them
+// where they are found would run the binning arithmetic for a wavefront
+// two-thirds idle: instead each hit's rotated bond (x', y') is compacted
+// (ballot + mbcnt) into a per-wavefront LDS buffer, and whenever it holds 64
+// bonds one full-width pass bins them.  The
 // histogram is privatised per workgroup in LDS, keeping only the bins a bond
 // shorter than r_max can reach (the paper notes that multi-dimensional
 // histograms outgrow the caches first): at 200 x 200 bins on [-3, 3)^2 with
@@ -33,13 +38,13 @@ struct PmftLds {
     int base[kPmftMaxRows + 1];
 };
 
-// Bins one bond (lanes with `hit`).
+constexpr int kBondBuf = 2 * kWave;  // rotated bonds buffered per wavefront
+
+// Bins one rotated bond (the calling lanes).
 template <bool LDS>
-__device__ __forceinline__ void bin_bond(const PmftArgs& a, const PmftLds& L, unsigned* hist,
-                                         float dx, float dy, float cs, float sn)
+__device__ __forceinline__ void bin_rotated(const PmftArgs& a, const PmftLds& L, unsigned* hist,
+                                            float xr, float yr)
 {
-    const float xr = fmaf(cs, dx, sn * dy);
-    const float yr = fmaf(cs, dy, -(sn * dx));
     const float tx = (xr + a.x_max) * a.inv_dx;
     const float ty = (yr + a.y_max) * a.inv_dy;
     if (!(tx >= 0.f && tx < (float)a.nbx && ty >= 0.f && ty < (float)a.nby)) return;
@@ -56,12 +61,51 @@ __device__ __forceinline__ void bin_bond(const PmftArgs& a, const PmftLds& L, un
     atomicAdd(&a.counts[ix * a.nby + iy], 1u);
 }
 
+// A wavefront's buffer of rotated bonds waiting to be binned.
+template <bool LDS>
+struct BondBuf {
+    float2* buf;  // [kBondBuf] in LDS
+    int nb;       // bonds buffered
+    int lane;
+
+    // Adds the calling lanes' bonds (mask m of the wavefront's lanes).
+    __device__ __forceinline__ void add(bool h, unsigned long long m, float xr, float yr)
+    {
+        if (h) buf[nb + (int)lane_prefix(m)] = make_float2(xr, yr);
+        nb += __popcll(m);
+    }
+    // Bins 64 bonds when that many are buffered, keeping the rest.
+    __device__ __forceinline__ void drain(const PmftArgs& a, const PmftLds& L, unsigned* hist)
+    {
+        if (nb < kWave) return;
+        wave_sync();
+        const float2 v = buf[lane];
+        const bool more = lane < nb - kWave;
+        float2 rest = make_float2(0.f, 0.f);
+        if (more) rest = buf[kWave + lane];
+        wave_sync();
+        if (more) buf[lane] = rest;
+        nb -= kWave;
+        bin_rotated<LDS>(a, L, hist, v.x, v.y);
+    }
+    __device__ __forceinline__ void finish(const PmftArgs& a, const PmftLds& L, unsigned* hist)
+    {
+        wave_sync();
+        if (lane < nb) {
+            const float2 v = buf[lane];
+            bin_rotated<LDS>(a, L, hist, v.x, v.y);
+        }
+        nb = 0;
+        wave_sync();
+    }
+};
+
 // The queries of one home cell against candidates [k0, k0 + 64 NS) of its
 // stencil.
 template <int NS, bool LDS>
 __device__ __forceinline__ void pmft_tile(const PmftArgs& a, const PairIn& in, const PmftLds& L,
-                                          const StencilLds& S, unsigned* hist, int C, int k0,
-                                          int q0, int q1, int lane)
+                                          const StencilLds& S, unsigned* hist, BondBuf<LDS>& B,
+                                          int C, int k0, int q0, int q1, int lane)
 {
     const PairGeom& G = a.geom;
     Slots<2, NS> c;
@@ -81,7 +125,11 @@ __device__ __forceinline__ void pmft_tile(const PmftArgs& a, const PairIn& in, c
                 const float dx = c.x[s] - qx, dy = c.y[s] - qy;
                 bool h = fmaf(dy, dy, dx * dx) < r2max;
                 if (a.excl) h = h && c.id[s] != qid;
-                if (h) bin_bond<LDS>(a, L, hist, dx, dy, ct, st);
+                // the bond in the query's frame, rotated by -theta
+                const float xr = fmaf(ct, dx, st * dy);
+                const float yr = fmaf(ct, dy, -(st * dx));
+                B.add(h, __ballot(h), xr, yr);
+                B.drain(a, L, hist);
             }
         }
     }
@@ -92,9 +140,11 @@ __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
 {
     extern __shared__ unsigned s_hist[];
     __shared__ PmftLds L;
+    __shared__ float2 s_bonds[kPmftWaves][kBondBuf];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     const PairGeom& G = a.geom;
+    BondBuf<LDS> B{s_bonds[wv], 0, lane};
     if (threadIdx.x < 9)
         L.off[threadIdx.x] = make_float4(G.off[threadIdx.x][0], G.off[threadIdx.x][1], 0.f, 0.f);
     if (LDS) {
@@ -115,14 +165,15 @@ __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
         const int ns = (C + kWave - 1) / kWave;
         switch (ns) {
 #define PPA_CASE(N) \
-    case N: pmft_tile<N, LDS>(a, in, L, S, s_hist, C, 0, q0, q1, lane); break;
+    case N: pmft_tile<N, LDS>(a, in, L, S, s_hist, B, C, 0, q0, q1, lane); break;
             PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4)
 #undef PPA_CASE
         default:
             for (int k0 = 0; k0 < C; k0 += kPmftChunk * kWave)
-                pmft_tile<kPmftChunk, LDS>(a, in, L, S, s_hist, C, k0, q0, q1, lane);
+                pmft_tile<kPmftChunk, LDS>(a, in, L, S, s_hist, B, C, k0, q0, q1, lane);
         }
     }
+    B.finish(a, L, s_hist);
     if (LDS) {
         __syncthreads();
         unsigned* out = a.partial + (size_t)blockIdx.x * a.words;
@@ -183,7 +234,8 @@ size_t pmft_lds_limit()
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             v > 0)
             limit = (size_t)v;
-        limit -= sizeof(PmftLds) + 256;  // the static part of the kernel's LDS
+        // the static part of the kernel's LDS
+        limit -= sizeof(PmftLds) + sizeof(float2) * kBondBuf * kPmftWaves + 256;
     }
     return limit;
 }
