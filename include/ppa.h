@@ -561,6 +561,13 @@ int ppa_batch_run(ppa_batch_plan* plan, const float* pts, void* ws, size_t ws_by
 int ppa_batch_config(ppa_batch_plan* plan, int32_t index, int32_t* n_configs, int32_t* chosen,
                      double* cell_scale, int32_t* blocks_per_cu);
 
+/* Block shape of configuration `index` (-1: the chosen one), which
+ * ppa_batch_config does not report: home cells per work-queue item and
+ * wavefronts per workgroup of the pair kernels.  Either pointer may be
+ * NULL.  Host only; does not change the chosen configuration. */
+int ppa_batch_config_shape(ppa_batch_plan* plan, int32_t index, int32_t* cells_per_item,
+                           int32_t* waves_per_workgroup);
+
 /* Autotuner: runs every configuration (one warm-up and `reps` timed runs,
  * HIP events on the stream, which it synchronizes) and selects the fastest
  * for later runs and graphs.  The NeighborList arguments are used as

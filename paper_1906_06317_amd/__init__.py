@@ -137,6 +137,7 @@ def lib():
             "ppa_batch_upload": [P, P, sz, P],
             "ppa_batch_run": [P, P, P, sz, P, P, P, P, P, i64, P, P],
             "ppa_batch_config": [P, i32, P, P, P, P],
+            "ppa_batch_config_shape": [P, i32, P, P],
             "ppa_batch_autotune": [P, P, P, sz, P, P, P, P, i64, P, i32, P, P],
             "ppa_batch_graph_create": [P, P, P, sz, P, P, P, P, P, i64, P,
                                        ctypes.POINTER(ctypes.c_void_p)],
@@ -929,8 +930,11 @@ class BatchPlan:
                             ctypes.c_int32())
         _check(lib().ppa_batch_config(self._h, int(index), ctypes.byref(n), ctypes.byref(c),
                                       ctypes.byref(scale), ctypes.byref(cap)))
+        run, waves = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ppa_batch_config_shape(self._h, -1, ctypes.byref(run), ctypes.byref(waves)))
         return {"n_configs": n.value, "chosen": c.value, "cell_scale": scale.value,
-                "blocks_per_cu": cap.value}
+                "blocks_per_cu": cap.value, "cells_per_item": run.value,
+                "waves_per_workgroup": waves.value}
 
     def autotune(self, points, reps=3, stream=None):
         """Times every launch configuration on these points and keeps the fastest."""
@@ -949,12 +953,33 @@ class BatchPlan:
             raise ValueError("points must hold every frame's rows")
         if hist is None:
             hist = torch.zeros((self.n_frames, self.bins), dtype=torch.int64, device=pts.device)
+        hist0 = hist.clone() if check else None
         o = self._out()
         _check(lib().ppa_batch_run(self._h, _ptr(pts), self.wptr, self.wlen, _ptr(hist), *o,
                                    _stream(stream)))
         if check:
-            _check(self.ws.status(stream))
+            st = self.ws.status(stream)
+            if st == PPA_ECAPACITY:
+                # the estimate was short: size the list from the count the run
+                # reported and run again (the histograms restart from their
+                # values before the call)
+                self._grow(int(self.n_pairs.item()))
+                hist.copy_(hist0)
+                o = self._out()
+                _check(lib().ppa_batch_run(self._h, _ptr(pts), self.wptr, self.wlen, _ptr(hist),
+                                           *o, _stream(stream)))
+                st = self.ws.status(stream)
+            _check(st)
         return hist, self.neighbor_list()
+
+    def _grow(self, pairs):
+        torch = _torch()
+        if self._graph:  # a captured graph points at the old buffers
+            lib().ppa_batch_graph_destroy(self._graph)
+            self._graph = None
+        self.capacity = int(pairs) + 1024
+        self.point_idx = torch.empty(self.capacity, dtype=torch.int32, device="cuda")
+        self.dist = torch.empty(self.capacity, dtype=torch.float32, device="cuda")
 
     def neighbor_list(self):
         np_ = int(self.n_pairs.item())

@@ -4,12 +4,17 @@
 // A plan fixes the frames and, per launch configuration, their cell grids;
 // the frame tables are uploaded into the caller's workspace once, after
 // which a run is a fixed sequence of kernels that can be captured in a HIP
-// graph and replayed with one launch.  The autotuner times the
-// configurations (cell width relative to r_max, and the number of resident
-// workgroups per CU of the pair kernels) on the caller's data and keeps the
-// fastest.  Configurations differ only in float32 rounding of the
-// cell-local coordinates, so their lists and histograms agree except for
-// pairs in the rounding band at r_max or at a bin edge.
+// graph and replayed with one launch.  The pair kernels take their home
+// cells from per-XCD work queues (runs of consecutive cells, handed out by
+// atomic counters, with stealing across XCDs), so one launch of each pass
+// covers every frame however uneven they are.  The autotuner times the
+// configurations on the caller's data and keeps the fastest; they vary the
+// cell width relative to r_max (at least r_max: the 27-cell stencil needs
+// it), the block shape (wavefronts per workgroup and the home cells per
+// queue item) and the resident workgroups per CU.  Configurations differ
+// only in float32 rounding of the cell-local coordinates, so their lists and
+// histograms agree except for pairs in the rounding band at r_max or at a
+// bin edge.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -25,10 +30,13 @@ namespace {
 struct BatchConfig {
     double cell_scale;  // cell width >= cell_scale * r_max
     int blocks_cap;     // resident workgroups per CU of the pair kernels (0: all that fit)
+    int run;            // home cells per work-queue item
+    int waves;          // wavefronts per workgroup of the pair kernels (2 or 4)
 };
 
 const BatchConfig kConfigs[] = {
-    {1.0, 0}, {1.0, 2}, {1.2, 0}, {1.2, 2}, {1.45, 0}, {1.45, 2},
+    {1.0, 0, 16, 4}, {1.0, 0, 4, 4},  {1.0, 0, 64, 4}, {1.0, 0, 16, 2},
+    {1.0, 2, 16, 4}, {1.2, 0, 16, 4}, {1.2, 0, 16, 2}, {1.45, 0, 16, 4},
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -145,11 +153,14 @@ void enqueue(const ppa_batch_plan* p, int ci, const float* pts, void* ws, const 
     B.nframes = p->nframes;
     B.ncells = T.ncells;
     B.r2max = p->r_max * p->r_max;
+    B.run = kConfigs[ci].run;
+    B.queue = W.counters;  // in the header, cleared by launch_zero above
     const int cap = kConfigs[ci].blocks_cap;
-    launch_count_batch(A, B, p->dim, p->excl, cap, s);
+    const int waves = kConfigs[ci].waves;
+    launch_count_batch(A, B, p->dim, p->excl, cap, waves, s);
     launch_scan_i64_total(A.counts, o.offsets, p->n_total, W.row_scan_flags, W.row_scan_ticket,
                           (unsigned long long*)o.n_pairs_dev, s);
-    launch_fill_batch(A, B, p->dim, p->excl, cap, s);
+    launch_fill_batch(A, B, p->dim, p->excl, cap, waves, s);
     if (p->sort_rows)
         launch_sort_rows(o.offsets, p->n_total, o.point_idx, o.dist, o.capacity, s);
 }
@@ -339,6 +350,17 @@ int ppa_batch_config(ppa_batch_plan* p, int32_t index, int32_t* n_configs, int32
     if (chosen) *chosen = p->chosen;
     if (cell_scale) *cell_scale = kConfigs[p->chosen].cell_scale;
     if (blocks_per_cu) *blocks_per_cu = kConfigs[p->chosen].blocks_cap;
+    return PPA_OK;
+}
+
+int ppa_batch_config_shape(ppa_batch_plan* p, int32_t index, int32_t* cells_per_item,
+                           int32_t* waves_per_workgroup)
+{
+    if (!p) return set_error(PPA_EINVAL, "plan is NULL");
+    if (index >= kNumConfigs) return set_error(PPA_EINVAL, "no configuration %d", index);
+    const int c = index >= 0 ? index : p->chosen;
+    if (cells_per_item) *cells_per_item = kConfigs[c].run;
+    if (waves_per_workgroup) *waves_per_workgroup = kConfigs[c].waves;
     return PPA_OK;
 }
 

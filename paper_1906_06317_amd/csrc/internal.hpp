@@ -65,7 +65,7 @@ struct CellList {
 
 struct Workspace {
     unsigned* status;             // device status bits
-    unsigned long long* counters; // [8] general counters (ticket, done)
+    unsigned long long* counters; // [24] general counters (k-NN deferred count, batch queues)
     CellList pts;
     CellList qry;                 // == pts for self queries
     // canonical-row mode: int64 exclusive scan of row counts
@@ -151,11 +151,14 @@ struct BatchGeom {
     int nframes;
     int ncells;        // all frames
     float r2max;
+    int run;           // home cells per work-queue item
+    unsigned long long* queue;  // [16] zeroed counters: 8 per-XCD queues per pass
 };
+// waves: wavefronts per workgroup (2 or 4)
 void launch_count_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
-                        hipStream_t s);
+                        int waves, hipStream_t s);
 void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
-                       hipStream_t s);
+                       int waves, hipStream_t s);
 
 // excl: 0 keep i == j, 1 points query themselves (drop the query's own
 // entry), 2 separate query points (drop j == i by index).

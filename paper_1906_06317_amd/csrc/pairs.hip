@@ -615,31 +615,49 @@ __global__ void __launch_bounds__(kBlock, 5) fill_kernel(const PairIn in, const 
 
 // ---------------------------------------------------------------------------
 // Batch: the same passes over the cells of many frames at once.  The home
-// cells of all frames form one global range; a wavefront walks its
-// contiguous share of it and switches geometry (grid, stencil offsets,
-// frame-local point indices, the frame's histogram) when its cells cross
-// into the next frame, which happens at most a few times per wavefront.
+// cells of all frames form one global range, cut into runs of B.run
+// consecutive cells; a wavefront switches geometry (grid, stencil offsets,
+// frame-local point indices, the frame's histogram) when a run takes it into
+// another frame.
 // ---------------------------------------------------------------------------
-// Home cells of a wavefront in a batch: the cells of XCD x (workgroups
-// dispatched round-robin over the 8 XCDs) are [c0, c1) = [x C / 8,
-// (x + 1) C / 8), cut into runs of kBatchRun consecutive cells dealt to the
-// XCD's wavefronts in turn (runs k0, k0 + kstride, ...): neighbouring runs
-// are in flight together and share stencil cells in the XCD's L2, while a
-// run rarely crosses into another frame.  Returns false for workgroups
-// beyond whole multiples of 8.
-constexpr int kBatchRun = 16;
+// Work queues of a batch pass.  The cells of XCD x (workgroups are
+// dispatched round-robin over the 8 XCDs) are [x C / 8, (x + 1) C / 8); its
+// runs are handed out in order by an atomic counter (queue[x]), so the runs
+// in flight on an XCD are neighbours sharing stencil cells in its L2, and a
+// wavefront that finds its own XCD's queue empty takes runs from the other
+// XCDs' queues in turn, so uneven frames (cheap and dear cells) finish
+// together.  Every wavefront ends when all eight queues are empty.
+struct RunQueue {
+    int x;       // XCD whose queue is being drained
+    int visited; // queues tried so far
+    int c0, c1;  // that XCD's cells
+    int nruns;
 
-__device__ __forceinline__ bool batch_chunks(int ncells, int wv, int& c0, int& c1, int& k0,
-                                             int& kstride)
-{
-    const int per = gridDim.x >> 3;
-    const int xcd = blockIdx.x & 7;
-    c0 = uniform((int)((long long)xcd * ncells / 8));
-    c1 = uniform((int)((long long)(xcd + 1) * ncells / 8));
-    k0 = uniform((int)(blockIdx.x >> 3) * kWavesPerBlock + wv);
-    kstride = per * kWavesPerBlock;
-    return (int)(blockIdx.x >> 3) < per;
-}
+    __device__ __forceinline__ void set(const BatchGeom& B, int xcd)
+    {
+        x = xcd;
+        c0 = (int)((long long)x * B.ncells / 8);
+        c1 = (int)((long long)(x + 1) * B.ncells / 8);
+        nruns = (c1 - c0 + B.run - 1) / B.run;
+    }
+    // The next run [t, te) for this wavefront; false when every queue is empty.
+    __device__ __forceinline__ bool next(const BatchGeom& B, unsigned long long* queue, int lane,
+                                         int& t, int& te)
+    {
+        for (;;) {
+            unsigned long long k = 0;
+            if (lane == 0) k = atomicAdd(&queue[x], 1ull);
+            const int kk = uniform((int)(k < (unsigned long long)nruns ? k : nruns));
+            if (kk < nruns) {
+                t = c0 + kk * B.run;
+                te = min(t + B.run, c1);
+                return true;
+            }
+            if (++visited == 8) return false;
+            set(B, (x + 1) & 7);
+        }
+    }
+};
 
 // Frame of global cell `tile`: the last f with cell_base[f] <= tile.
 __device__ __forceinline__ int frame_of(const BatchGeom& B, int tile)
@@ -673,33 +691,38 @@ __device__ __forceinline__ GeomView load_frame(const BatchGeom& B, int f, float4
     return v;
 }
 
-template <int DIM, int EXCL>
-__global__ void __launch_bounds__(kBlock, 5) count_batch_kernel(const PairIn in, const BatchGeom B,
-                                                             int32_t* __restrict__ counts)
+// Row lengths of a batch; WPB wavefronts per workgroup.
+template <int DIM, int EXCL, int WPB>
+__global__ void __launch_bounds__(WPB * kWave, 5) count_batch_kernel(
+    const PairIn in, const BatchGeom B, int32_t* __restrict__ counts)
 {
-    __shared__ float4 s_off[kWavesPerBlock][27];
-    __shared__ StencilLds s_st[kWavesPerBlock];
-    __shared__ float4 s_q[kWavesPerBlock][kWave];
+    __shared__ float4 s_off[WPB][27];
+    __shared__ StencilLds s_st[WPB];
+    __shared__ float4 s_q[WPB][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     StencilLds& S = s_st[wv];
     float4* off = s_off[wv];
-    int c0, c1, k0, kstride;
-    if (!batch_chunks(B.ncells, wv, c0, c1, k0, kstride)) return;
-    int f = -1, next = -1;
+    RunQueue R;
+    R.visited = 0;
+    R.set(B, blockIdx.x & 7);
+    int f = -1, cur = 0, next = -1;
     GeomView V;
-    for (int k = k0; c0 + k * kBatchRun < c1; k += kstride)
-    for (int tile = c0 + k * kBatchRun, te = min(tile + kBatchRun, c1); tile < te; ++tile) {
-        if (tile >= next) {
-            f = frame_of(B, tile);
-            V = load_frame(B, f, off, lane);
-            next = B.cell_base[f + 1];
+    int t, te;
+    while (R.next(B, B.queue, lane, t, te)) {
+        for (int tile = t; tile < te; ++tile) {
+            if (tile < cur || tile >= next) {
+                f = frame_of(B, tile);
+                V = load_frame(B, f, off, lane);
+                cur = B.cell_base[f];
+                next = B.cell_base[f + 1];
+            }
+            const int q0 = in.q_start[tile];
+            const int q1 = in.q_start[tile + 1];
+            if (q0 == q1) continue;
+            const int C = stencil<DIM>(in, V, tile, lane, S);
+            count_cell<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, s_q[wv], counts);
         }
-        const int q0 = in.q_start[tile];
-        const int q1 = in.q_start[tile + 1];
-        if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, V, tile, lane, S);
-        count_cell<DIM, EXCL>(in, V, S, off, C, q0, q1, lane, s_q[wv], counts);
     }
 }
 
@@ -718,14 +741,15 @@ __device__ __forceinline__ void merge_wave_hist(unsigned* h, unsigned long long*
     wave_sync();
 }
 
-// NeighborList and per-frame RDF (histograms [nframes][bins]) of a batch.
-template <int DIM, int EXCL>
-__global__ void __launch_bounds__(kBlock, 5) fill_batch_kernel(const PairIn in, const BatchGeom B,
-                                                            const FillOut O)
+// NeighborList and per-frame RDF (histograms [nframes][bins]) of a batch;
+// WPB wavefronts per workgroup.
+template <int DIM, int EXCL, int WPB>
+__global__ void __launch_bounds__(WPB * kWave, 5) fill_batch_kernel(
+    const PairIn in, const BatchGeom B, const FillOut O)
 {
     extern __shared__ unsigned s_dyn[];  // one histogram per wavefront when bins are few
-    __shared__ float4 s_off[kWavesPerBlock][27];
-    __shared__ FillLds<true> s_w[kWavesPerBlock];
+    __shared__ float4 s_off[WPB][27];
+    __shared__ FillLds<true> s_w[WPB];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     StencilLds& S = s_w[wv].st;
@@ -736,35 +760,39 @@ __global__ void __launch_bounds__(kBlock, 5) fill_batch_kernel(const PairIn in, 
         for (int b = lane; b < O.bins; b += kWave) h[b] = 0u;
     if (lane < kHitCap / 64) s_w[wv].starts[lane] = 0ull;
     wave_sync();
-    int c0, c1, k0, kstride;
-    if (!batch_chunks(B.ncells, wv, c0, c1, k0, kstride)) return;
     Filler<DIM, EXCL, true, true> F(s_w[wv], O, h, lane);
-    int f = -1, next = -1;
+    RunQueue R;
+    R.visited = 0;
+    R.set(B, blockIdx.x & 7);
+    int f = -1, cur = 0, next = -1;
     GeomView V;
-    for (int k = k0; c0 + k * kBatchRun < c1; k += kstride)
-    for (int tile = c0 + k * kBatchRun, te = min(tile + kBatchRun, c1); tile < te; ++tile) {
-        if (tile >= next) {
-            // buffered hits belong to the old frame: write them and its bins first
-            if (F.nh > 0) F.flush();
-            if (lds_hist && f >= 0) merge_wave_hist(h, F.ghist, O.bins, lane);
-            f = frame_of(B, tile);
-            V = load_frame(B, f, off, lane);
-            F.ghist = O.hist + (size_t)f * O.bins;
-            F.id_base = uniform(B.frames[f].point_base);
-            next = B.cell_base[f + 1];
-        }
-        const int q0 = in.q_start[tile];
-        const int q1 = in.q_start[tile + 1];
-        if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, V, tile, lane, S);
-        const int ns = (C + kWave - 1) / kWave;
-        switch (ns) {
+    int t, te;
+    while (R.next(B, B.queue + 8, lane, t, te)) {
+        for (int tile = t; tile < te; ++tile) {
+            if (tile < cur || tile >= next) {
+                // buffered hits belong to the old frame: write them and its bins first
+                if (F.nh > 0) F.flush();
+                if (lds_hist && f >= 0) merge_wave_hist(h, F.ghist, O.bins, lane);
+                f = frame_of(B, tile);
+                V = load_frame(B, f, off, lane);
+                F.ghist = O.hist + (size_t)f * O.bins;
+                F.id_base = uniform(B.frames[f].point_base);
+                cur = B.cell_base[f];
+                next = B.cell_base[f + 1];
+            }
+            const int q0 = in.q_start[tile];
+            const int q1 = in.q_start[tile + 1];
+            if (q0 == q1) continue;
+            const int C = stencil<DIM>(in, V, tile, lane, S);
+            const int ns = (C + kWave - 1) / kWave;
+            switch (ns) {
 #define PPA_CASE(N) \
     case N: fill_tile<DIM, EXCL, true, true, N>(in, V, S, off, C, q0, q1, F); break;
-            PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
-            PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
+                PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5)
+                PPA_CASE(6) PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
 #undef PPA_CASE
-        default: fill_chunked<DIM, EXCL, true, true>(in, V, S, off, C, q0, q1, F);
+            default: fill_chunked<DIM, EXCL, true, true>(in, V, S, off, C, q0, q1, F);
+            }
         }
     }
     if (F.nh > 0) F.flush();
@@ -847,9 +875,11 @@ void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s)
 #undef PPA_COUNT
 }
 
-static int capped(int blocks, int blocks_cap)
+// Workgroups for a batch pass: as many as fit at once (times the cap per CU
+// when one is set), a multiple of 8; the queues hand out the work.
+template <typename K>
+static int batch_blocks(K kernel, int threads, size_t lds, int blocks_cap)
 {
-    if (blocks_cap <= 0) return blocks;
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;
@@ -858,45 +888,53 @@ static int capped(int blocks, int blocks_cap)
                   ? prop.multiProcessorCount
                   : 256;
     }
-    const int cap = cus * blocks_cap;
-    return blocks < cap ? blocks : cap;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (blocks_cap > 0 && per_cu > blocks_cap) per_cu = blocks_cap;
+    return (cus * per_cu + 7) / 8 * 8;
 }
 
-template <int DIM, int EXCL>
+template <int DIM, int EXCL, int WPB>
 static void count_batch_t(const PairIn& in, const BatchGeom& b, int32_t* counts, int blocks_cap,
                           hipStream_t s)
 {
-    auto k = count_batch_kernel<DIM, EXCL>;
-    const int blocks = capped(resident_blocks(k, 0, b.ncells), blocks_cap);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), 0, s, in, b, counts);
+    auto k = count_batch_kernel<DIM, EXCL, WPB>;
+    const int blocks = batch_blocks(k, WPB * kWave, 0, blocks_cap);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(WPB * kWave), 0, s, in, b, counts);
 }
 
-template <int DIM, int EXCL>
+template <int DIM, int EXCL, int WPB>
 static void fill_batch_t(const PairIn& in, const BatchGeom& b, const FillOut& o, int blocks_cap,
                          hipStream_t s)
 {
     const size_t lds =
-        o.bins <= kMaxBatchLdsBins ? sizeof(unsigned) * (size_t)o.bins * kWavesPerBlock : 0;
-    auto k = fill_batch_kernel<DIM, EXCL>;
-    const int blocks = capped(resident_blocks(k, lds, b.ncells), blocks_cap);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), lds, s, in, b, o);
+        o.bins <= kMaxBatchLdsBins ? sizeof(unsigned) * (size_t)o.bins * WPB : 0;
+    auto k = fill_batch_kernel<DIM, EXCL, WPB>;
+    const int blocks = batch_blocks(k, WPB * kWave, lds, blocks_cap);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(WPB * kWave), lds, s, in, b, o);
 }
 
 void launch_count_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
-                        hipStream_t s)
+                        int waves, hipStream_t s)
 {
     const PairIn in = make_in(a);
+#define PPA_CB(D, E)                                                         \
+    do {                                                                     \
+        if (waves == 2) count_batch_t<D, E, 2>(in, b, a.counts, blocks_cap, s); \
+        else count_batch_t<D, E, 4>(in, b, a.counts, blocks_cap, s);        \
+    } while (0)
     if (dim == 3) {
-        if (excl) count_batch_t<3, 1>(in, b, a.counts, blocks_cap, s);
-        else count_batch_t<3, 0>(in, b, a.counts, blocks_cap, s);
+        if (excl) PPA_CB(3, 1); else PPA_CB(3, 0);
     } else {
-        if (excl) count_batch_t<2, 1>(in, b, a.counts, blocks_cap, s);
-        else count_batch_t<2, 0>(in, b, a.counts, blocks_cap, s);
+        if (excl) PPA_CB(2, 1); else PPA_CB(2, 0);
     }
+#undef PPA_CB
 }
 
 void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl, int blocks_cap,
-                       hipStream_t s)
+                       int waves, hipStream_t s)
 {
     const PairIn in = make_in(a);
     FillOut o;
@@ -909,13 +947,17 @@ void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl,
     o.bins = a.bins;
     o.r_min = a.r_min;
     o.inv_dr = a.inv_dr;
+#define PPA_FB(D, E)                                                 \
+    do {                                                             \
+        if (waves == 2) fill_batch_t<D, E, 2>(in, b, o, blocks_cap, s); \
+        else fill_batch_t<D, E, 4>(in, b, o, blocks_cap, s);        \
+    } while (0)
     if (dim == 3) {
-        if (excl) fill_batch_t<3, 1>(in, b, o, blocks_cap, s);
-        else fill_batch_t<3, 0>(in, b, o, blocks_cap, s);
+        if (excl) PPA_FB(3, 1); else PPA_FB(3, 0);
     } else {
-        if (excl) fill_batch_t<2, 1>(in, b, o, blocks_cap, s);
-        else fill_batch_t<2, 0>(in, b, o, blocks_cap, s);
+        if (excl) PPA_FB(2, 1); else PPA_FB(2, 0);
     }
+#undef PPA_FB
 }
 
 void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s)

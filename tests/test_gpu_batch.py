@@ -199,10 +199,11 @@ def test_non_finite_and_capacity_are_reported(ppa):
     with pytest.raises(ppa.PPAError) as e:
         plan.run(bad)
     assert e.value.code == ppa.PPA_ENONFINITE
+    # the C ABI reports the overflow (the binding's run() then grows the list
+    # and runs again; test_capacity_retry_and_block_shapes covers that)
     small, pts2 = _plan(ppa, frames, capacity=1000)
-    with pytest.raises(ppa.PPAError) as e:
-        small.run(pts2)
-    assert e.value.code == ppa.PPA_ECAPACITY
+    small.run(pts2, check=False)
+    assert small.ws.status() == ppa.PPA_ECAPACITY
     assert int(small.n_pairs.item()) > 1000  # the true count is still reported
 
 
@@ -235,3 +236,19 @@ def test_sorted_rows_and_graph(ppa):
         torch.cuda.synchronize()
         assert srt.ws.status() == 0
         np.testing.assert_array_equal(srt.neighbor_list().point_idx.cpu().numpy(), si)
+
+
+def test_capacity_retry_and_block_shapes(ppa):
+    """A plan sized too small for its list grows it and runs again (the
+    histograms counted once); every configuration reports its block shape."""
+    frames = _frames(17, 5, 1500, 4000)
+    plan, pts = _plan(ppa, frames, capacity=1000)
+    hist, nl = plan.run(pts)
+    assert plan.capacity > 1000
+    _check_against_oracle(frames, hist, nl, plan.offsets_host)
+    shapes = set()
+    for c in range(plan.config()["n_configs"]):
+        cfg = plan.config(c)
+        assert cfg["cells_per_item"] >= 1 and cfg["waves_per_workgroup"] in (2, 4)
+        shapes.add((cfg["cells_per_item"], cfg["waves_per_workgroup"]))
+    assert len(shapes) >= 3
