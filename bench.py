@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the fill kernel's source hash (for the traffic record) and exit")
+    ap.add_argument("--only", choices=["pmft2d", "pmft3", "correlation", "steinhardt", "clusters",
+                                       "batched", "smooth_rdf", "small"],
+                    help="run one row alone and print its JSON (for profiling that row)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for "
                          "memory-traffic counters)")
@@ -295,6 +298,9 @@ def headline(args, ppa, hip):
     rows = {
         "ball_rdf": {"ms": ball_ms, "pairs_per_s": P / (ball_ms * 1e-3),
                      "note": "cell build + count + scan + fill with fused RDF",
+                     "end_to_end_achieved_GBps": alg_bytes / (ball_ms * 1e-3) / 1e9,
+                     "end_to_end_frac": alg_bytes / (ball_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "fill_kernel_frac": achieved / HBM_PEAK_GBS,
                      "sorted_rows_ms": sorted_ms,
                      "sort_rows_ms": sorted_ms - ball_ms},
         "knn": {"workload": "same system, k=12 (own cell list)", "ms_in_step": None,
@@ -742,6 +748,137 @@ def row_smooth(ppa, hip):
                          "note": "one exp2 per window term (quarter-rate transcendental peak)"}}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def row_small(ppa, hip):
+    """The small configuration (N = 4096 uniform, density 0.8, cubic): ball
+    r_max = 3 writing the list with the 100-bin RDF in the same call, and
+    the oracle over every row (brute force, FP64, all host threads)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    s = workloads.small_uniform()
+    n = s.points.shape[0]
+    box = ppa.Box(s.L, s.tilt, s.dim)
+    pts = torch.as_tensor(s.points).cuda()
+    counts0, nl0 = ppa.rdf_counts(box, pts, 100, 3.0, neighbor_list=True)
+    P = nl0.n_pairs
+    ws = ppa.Workspace()
+    wptr, wlen = ws.get(ppa.workspace_bytes(box, n, 0, 3.0, ppa.PPA_WS_NLIST))
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    rc_ = torch.empty(n, dtype=torch.int32, device="cuda")
+    pidx = torch.empty(P, dtype=torch.int32, device="cuda")
+    dist = torch.empty(P, dtype=torch.float32, device="cuda")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    hist = torch.zeros(100, dtype=torch.int64, device="cuda")
+    cb = box.c()
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    ms = timed(lambda: L.ppa_rdf(ctypes.byref(cb), p(pts), n, None, n, 100, 0.0, 3.0, 1, 0, wptr,
+                                 wlen, p(hist), p(off), p(rc_), p(pidx), p(dist), P, p(npairs),
+                                 sptr), 50, warmup=3)
+    if ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
+    ob = oracle.make_box(s.L, s.tilt, s.dim)
+    t = time.perf_counter()
+    _, idx, _ = oracle.ball_query(ob, s.points, 3.0)
+    oracle.rdf_counts(ob, s.points, 100, 3.0)
+    cpu_s = time.perf_counter() - t
+    return {"workload": "uniform N=4096, density 0.8, cubic; ball r_max=3 -> NeighborList + RDF "
+                        "100 bins on [0,3) in one call", "pairs": P, "ms": ms,
+            "pairs_per_s": P / (ms * 1e-3), "note": "latency-bound: a few microseconds of work",
+            "oracle": {"value": int(idx.shape[0]) / cpu_s, "unit": "pairs/s",
+                       "cores": oracle.num_threads(), "kind": "oracle",
+                       "sample": f"every row (brute force, FP64), ball list + RDF, {cpu_s:.2f} s"}}
+
+
+def oracle_rows(budget_s=4.0):
+    """The oracle timed on bounded samples of the other configurations
+    (brute force, FP64, all host threads): the 2D PMFT's query rows, the
+    batched trajectory's rows from every 16th frame, and the smoothed RDF's
+    rows (forward) and gradient rows."""
+    import numpy as np
+
+    import oracle
+    from paper_1906_06317_amd import workloads
+    rng = np.random.default_rng(7)
+    out = {"cores": oracle.num_threads(), "cpu_model": _cpu_model()}
+
+    def scaled(fn, nq0):
+        """Runs fn(nq) at nq0 rows, then at a size that fills the budget."""
+        dt, w = fn(nq0)
+        nq = int(max(nq0, nq0 * budget_s / max(dt, 1e-3)))
+        dt, w = fn(nq)
+        return nq, dt, w
+
+    s = workloads.fluid_2d()
+    ob = oracle.make_box(s.L, s.tilt, s.dim)
+
+    def pmft(nq):
+        rows = rng.choice(s.points.shape[0], nq, replace=False)
+        t = time.perf_counter()
+        lo, _, _ = oracle.pmft2d_counts(ob, s.points, s.points[rows], s.theta[rows], 200, 200,
+                                        3.0, 3.0, 3.0, exclude_ii=False)
+        return time.perf_counter() - t, int(lo.sum()) - nq  # own entries at r = 0
+    nq, dt, w = scaled(pmft, 64)
+    out["pmft2d"] = {"value": w / dt, "unit": "pairs/s", "kind": "oracle",
+                     "sample": f"{nq} random query rows of the 2D fluid (200x200 PMFT counts), "
+                               f"{dt:.1f} s"}
+
+    frames = workloads.trajectory()
+
+    def traj(nq):
+        pairs, t = 0, time.perf_counter()
+        for f in range(0, len(frames), 16):
+            fs = frames[f]
+            m = min(nq, fs.points.shape[0])
+            rows = rng.choice(fs.points.shape[0], m, replace=False)
+            fb = oracle.make_box(fs.L, fs.tilt, fs.dim)
+            _, idx, _ = oracle.ball_query(fb, fs.points, 2.5, query_points=fs.points[rows],
+                                          exclude_ii=False)
+            oracle.rdf_counts(fb, fs.points, 128, 2.5, query_points=fs.points[rows],
+                              exclude_ii=False)
+            pairs += int(idx.shape[0]) - m
+        return time.perf_counter() - t, pairs
+    nq, dt, w = scaled(traj, 16)
+    out["batched"] = {"value": w / dt, "unit": "pairs/s", "kind": "oracle",
+                      "sample": f"{nq} random rows of each of 16 frames (every 16th), ball list + "
+                                f"RDF per frame, {dt:.1f} s"}
+
+    sc, _ = workloads.smooth_target_pair()
+    sb = oracle.make_box(sc.L, sc.tilt, sc.dim)
+    pts64 = sc.points.astype(np.float64)
+
+    def smooth(nq):
+        rows = rng.choice(sc.points.shape[0], nq, replace=False)
+        t = time.perf_counter()
+        for k in rows:
+            oracle.smooth_rdf_row(sb, sc.points, int(k), pts64[k], 200, 3.0, 0.02)
+        oracle.smooth_rdf_grad(sb, sc.points, 200, 3.0, 0.02, np.ones(200), rows=rows)
+        dt = time.perf_counter() - t
+        # the rows' pairs within r_max + 8 sigma (counted after the timing)
+        _, idx, _ = oracle.ball_query(sb, sc.points, 3.16, query_points=sc.points[rows],
+                                      exclude_ii=False)
+        return dt, int(idx.shape[0]) - nq
+    nq, dt, w = scaled(smooth, 16)
+    out["smooth_rdf"] = {"value": w / dt, "unit": "pairs/s (forward row + gradient row)",
+                         "kind": "oracle",
+                         "sample": f"{nq} random rows of the perturbed simple-cubic system, one "
+                                   f"forward row and one gradient row each, {dt:.1f} s"}
+    return out
+
+
 def main():
     args = parse()
     if args.source_hash:
@@ -763,6 +900,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        fns = {"pmft2d": lambda: row_pmft(ppa, hip),
+               "pmft3": lambda: row_pmft3(ppa, hip, global_atomic_peak(ppa)),
+               "correlation": lambda: row_correlation(ppa, hip),
+               "steinhardt": lambda: row_steinhardt(ppa, hip),
+               "clusters": lambda: row_clusters(ppa, hip),
+               "batched": lambda: row_batched(ppa, hip),
+               "smooth_rdf": lambda: row_smooth(ppa, hip),
+               "small": lambda: row_small(ppa, hip)}
+        print(json.dumps({"row": args.only, **fns[args.only]()}), flush=True)
+        return
     line, rows, sysm = headline(args, ppa, hip)
     copy_gbs = copy_bandwidth()
     line["roofline"]["measured_copy_GBps"] = copy_gbs
@@ -789,7 +937,10 @@ def main():
         rows["clusters"] = row_clusters(ppa, hip)
         rows["batched"] = row_batched(ppa, hip)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
+        rows["small"] = row_small(ppa, hip)
         rows["paper_context"] = paper_context(ppa)
+        if not args.no_cpu_baseline:
+            rows["oracle"] = oracle_rows()
     line["rows"] = rows
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_seconds)
