@@ -179,6 +179,29 @@ def test_full_size_perturbed_lattice(ppa):
     rows = np.sort(np.random.default_rng(6).choice(n, 300, replace=False))
     g_ref = oracle.smooth_rdf_grad(_obox(s), s.points, BINS, R_MAX, SIGMA, gh, rows=rows)
     _check_grad(g[rows], g_ref)
+    # and against FP64 finite differences of the loss itself on this system:
+    # moving particle k changes h only through its own pairs (both orders),
+    # which smooth_rdf_row gives; Richardson-extrapolated central differences
+    ob = _obox(s)
+
+    def loss_at(k, pk):
+        hk = h_ref - oracle.smooth_rdf_row(ob, s.points, k, s.points[k].astype(np.float64), BINS,
+                                           R_MAX, SIGMA) \
+            + oracle.smooth_rdf_row(ob, s.points, k, pk, BINS, R_MAX, SIGMA)
+        return float(((hk * scale - t) ** 2).sum())
+
+    floor = 5e-5 * np.abs(g_ref).max()
+    for k in np.random.default_rng(8).choice(n, 4, replace=False):
+        for a in range(3):
+            def cd(e):
+                p = s.points[k].astype(np.float64).copy()
+                p[a] += e
+                lp = loss_at(k, p)
+                p[a] -= 2 * e
+                return (lp - loss_at(k, p)) / (2 * e)
+            eps = 2e-4
+            fd = (4 * cd(eps / 2) - cd(eps)) / 3
+            assert abs(g[k, a] - fd) <= GRAD_TOL * abs(fd) + floor, (k, a, g[k, a], fd)
 
 
 def test_non_finite_input_is_reported(ppa):
