@@ -224,6 +224,23 @@ bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r)
     return err <= 0.5e-5 * r * r;
 }
 
+// Wavefronts sharing each home cell's queries in the ball query's passes.
+// One wavefront per cell leaves most of the chip idle when there are few
+// cells (a small system, or a cutoff that is large against the box): then
+// each cell's queries are split between several wavefronts, each loading
+// the cell's stencil, up to about 8192 wavefronts in all and down to about
+// four queries per wavefront.
+int pair_split(long long ncells, long long nq)
+{
+    constexpr long long kTargetWaves = 8192;
+    if (ncells <= 0 || ncells >= kTargetWaves) return 1;
+    long long s = kTargetWaves / ncells;
+    const long long by_queries = nq / ncells / 4;
+    if (s > by_queries) s = by_queries;
+    if (s > 16) s = 16;
+    return s < 1 ? 1 : (int)s;
+}
+
 }  // namespace ppa
 
 using namespace ppa;
@@ -310,6 +327,7 @@ int run_pairs(const QueryCall& c)
     memcpy(A.geom.off, g.off, sizeof(A.geom.off));
     A.geom.r2max = c.r_max * c.r_max;
     A.geom.dot = expanded_test_ok(bp, g, c.r_max) ? 1 : 0;
+    A.geom.split = pair_split(g.ncells, c.nq);
     A.offsets = c.offsets;
     A.point_idx = c.point_idx;
     A.dist = c.dist;

@@ -124,6 +124,7 @@ struct PairGeom {
     float off[27][3];    // stencil offsets M (delta / n)
     float r2max;
     int dot;             // 1: expanded in/out test (its error bound passed on the host)
+    int split;           // ball query: wavefronts sharing a home cell's queries (0, 1: one)
 };
 
 struct PairArgs {

@@ -114,6 +114,33 @@ __device__ __forceinline__ void wave_tiles_interleaved(int ncells, int wv, int& 
     if ((int)(blockIdx.x >> 3) >= per) t1 = t0;  // launches are whole multiples of 8
 }
 
+// Work item v of a pass whose home cells are shared by `split` wavefronts
+// each: its cell, and its part of the cell's queries [q0, q1) (contiguous
+// parts of equal length; the last ones may be empty).  split <= 1: item v is
+// cell v with all its queries.
+struct CellPart {
+    int tile, qc, q0, q1;  // cell, its first query, this part's queries
+};
+
+__device__ __forceinline__ CellPart cell_part(const PairIn& in, int v, int split)
+{
+    CellPart p;
+    if (split <= 1) {
+        p.tile = v;
+        p.qc = p.q0 = in.q_start[v];
+        p.q1 = in.q_start[v + 1];
+        return p;
+    }
+    p.tile = uniform(v / split);
+    const int part = v - p.tile * split;
+    p.qc = in.q_start[p.tile];
+    const int end = in.q_start[p.tile + 1];
+    const int per = (end - p.qc + split - 1) / split;
+    p.q0 = min(end, p.qc + part * per);
+    p.q1 = min(end, p.q0 + per);
+    return p;
+}
+
 // Stencil slot -> offset code d = (dx+1) + 3 (dy+1) + 9 (dz+1): the home
 // cell (centre code) is slot 0 and takes the place of code 0.
 __device__ __forceinline__ int stencil_code(int s, int nsten)

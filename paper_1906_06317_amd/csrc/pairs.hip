@@ -217,14 +217,14 @@ __global__ void __launch_bounds__(kBlock, 6) count_kernel(const PairIn in, const
                                          G.off[threadIdx.x][2], 0.f);
     __syncthreads();
     const GeomView V = view_of(G);
+    const int split = G.split > 1 ? G.split : 1;
     int t0, t1, stride;
-    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
-    for (int tile = t0; tile < t1; tile += stride) {
-        const int q0 = in.q_start[tile];
-        const int q1 = in.q_start[tile + 1];
-        if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, V, tile, lane, S);
-        count_cell<DIM, EXCL>(in, V, S, s_off, C, q0, q1, lane, s_q[wv], counts);
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells * split, wv, t0, t1, stride);
+    for (int v = t0; v < t1; v += stride) {
+        const CellPart P = cell_part(in, v, split);
+        if (P.q0 == P.q1) continue;
+        const int C = stencil<DIM>(in, V, P.tile, lane, S);
+        count_cell<DIM, EXCL>(in, V, S, s_off, C, P.q0, P.q1, lane, s_q[wv], counts);
     }
 }
 
@@ -437,9 +437,10 @@ struct Filler {
     }
 };
 
+// Queries [q0, q1) of the home cell whose first query is qc.
 template <int DIM, int EXCL, bool NL, bool HIST, int NS>
 __device__ __forceinline__ void fill_tile(const PairIn& in, const GeomView& G, const StencilLds& S,
-                                          const float4* off, int C, int q0, int q1,
+                                          const float4* off, int C, int qc, int q0, int q1,
                                           Filler<DIM, EXCL, NL, HIST>& F)
 {
     const int lane = F.lane;
@@ -457,7 +458,7 @@ __device__ __forceinline__ void fill_tile(const PairIn& in, const GeomView& G, c
         }
         for (int t = 0; t < Q.n; ++t) {
             // position of the query's own entry in slot 0 (home cell first)
-            const int self = (c0 - q0) + t < kWave ? (c0 - q0) + t : -1;
+            const int self = (c0 - qc) + t < kWave ? (c0 - qc) + t : -1;
             if constexpr (NL) {
                 const int need = lane_of(rl_v, t);  // the row, from the count pass
                 if (need > kHitCap) {
@@ -475,7 +476,7 @@ __device__ __forceinline__ void fill_tile(const PairIn& in, const GeomView& G, c
                     if (F.nh + need + need_b > kHitCap || F.nrows + 2 > kRows) F.flush();
                     const int rsa = F.nh;
                     const int rsb = rsa + need;
-                    const int self_b = (c0 - q0) + t + 1 < kWave ? (c0 - q0) + t + 1 : -1;
+                    const int self_b = (c0 - qc) + t + 1 < kWave ? (c0 - qc) + t + 1 : -1;
                     const bool by_id = EXCL == 2 || (EXCL == 1 && self_b < 0);
                     const Query qa = Q.get<DIM>(t, r2max);
                     const Query qb = Q.get<DIM>(t + 1, r2max);
@@ -578,22 +579,23 @@ __global__ void __launch_bounds__(kBlock, 5) fill_kernel(const PairIn in, const 
     }
     Filler<DIM, EXCL, NL, HIST> F(s_w[wv], O, lds_hist ? s_hist : nullptr, lane);
     const GeomView V = view_of(G);
+    const int split = G.split > 1 ? G.split : 1;
     int t0, t1, stride;
-    wave_tiles_interleaved<kWavesPerBlock>(G.ncells, wv, t0, t1, stride);
-    for (int tile = t0; tile < t1; tile += stride) {
-        const int q0 = in.q_start[tile];
-        const int q1 = in.q_start[tile + 1];
-        if (q0 == q1) continue;
-        const int C = stencil<DIM>(in, V, tile, lane, S);
+    wave_tiles_interleaved<kWavesPerBlock>(G.ncells * split, wv, t0, t1, stride);
+    for (int v = t0; v < t1; v += stride) {
+        const CellPart P = cell_part(in, v, split);
+        if (P.q0 == P.q1) continue;
+        const int C = stencil<DIM>(in, V, P.tile, lane, S);
         const int ns = (C + kWave - 1) / kWave;
         switch (ns) {
-#define PPA_CASE(N) \
-    case N: fill_tile<DIM, EXCL, NL, HIST, N>(in, V, S, s_off, C, q0, q1, F); break;
+#define PPA_CASE(N)                                                                        \
+    case N: fill_tile<DIM, EXCL, NL, HIST, N>(in, V, S, s_off, C, P.qc, P.q0, P.q1, F); \
+        break;
             PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5) PPA_CASE(6)
             PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
 #undef PPA_CASE
             static_assert(kFillSlots == 10, "the cases above cover 0..kFillSlots");
-        default: fill_chunked<DIM, EXCL, NL, HIST>(in, V, S, s_off, C, q0, q1, F);
+        default: fill_chunked<DIM, EXCL, NL, HIST>(in, V, S, s_off, C, P.q0, P.q1, F);
         }
     }
     if (F.nh > 0) F.flush();
@@ -787,7 +789,7 @@ __global__ void __launch_bounds__(WPB * kWave, 5) fill_batch_kernel(
             const int ns = (C + kWave - 1) / kWave;
             switch (ns) {
 #define PPA_CASE(N) \
-    case N: fill_tile<DIM, EXCL, true, true, N>(in, V, S, off, C, q0, q1, F); break;
+    case N: fill_tile<DIM, EXCL, true, true, N>(in, V, S, off, C, q0, q0, q1, F); break;
                 PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4) PPA_CASE(5)
                 PPA_CASE(6) PPA_CASE(7) PPA_CASE(8) PPA_CASE(9) PPA_CASE(10)
 #undef PPA_CASE
@@ -836,7 +838,7 @@ template <int DIM, int EXCL>
 void launch_count_t(const PairIn& in, const PairGeom& g, int32_t* counts, hipStream_t s)
 {
     auto k = count_kernel<DIM, EXCL>;
-    const int blocks = resident_blocks(k, 0, g.ncells);
+    const int blocks = resident_blocks(k, 0, (long long)g.ncells * (g.split > 1 ? g.split : 1));
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), 0, s, in, g, counts);
 }
 
@@ -847,7 +849,7 @@ void launch_fill_t(const PairIn& in, const PairGeom& g, const FillOut& o, bool n
     const size_t lds = (hist && o.bins <= kMaxLdsBins) ? sizeof(unsigned) * (size_t)o.bins : 0;
     auto k = nl ? (hist ? fill_kernel<DIM, EXCL, true, true> : fill_kernel<DIM, EXCL, true, false>)
                 : fill_kernel<DIM, EXCL, false, true>;
-    const int blocks = resident_blocks(k, lds, g.ncells);
+    const int blocks = resident_blocks(k, lds, (long long)g.ncells * (g.split > 1 ? g.split : 1));
     hipLaunchKernelGGL(k, dim3(blocks), dim3(kBlock), lds, s, in, g, o);
 }
 
