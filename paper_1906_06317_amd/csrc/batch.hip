@@ -43,9 +43,50 @@ constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 struct ConfigTables {
     std::vector<FrameInfo> frames;
     std::vector<int> cell_base;  // [nframes + 1]
+    std::vector<ChunkInfo> chunks;  // frames whose cells are counted in LDS, by chunks
     int ncells;
-    size_t frames_off, cell_base_off;  // workspace offsets of the device copies
+    int max_chunk_cells;   // cells of the largest chunked frame
+    int64_t part_entries;  // entries of the partial-count array the chunks use
+    bool global_frames;    // some frame counts with global atomics
+    size_t frames_off, cell_base_off, chunks_off;  // workspace offsets of the device copies
 };
+
+// Splits the frames into chunks for the cell build: each frame with at most
+// kChunkMaxCells cells gets ceil(points / kChunkPoints) chunks, each with a
+// row of the frame's cells in the partial-count array.
+void make_chunks(ConfigTables& T, const std::vector<int>& point_base, int nframes)
+{
+    T.chunks.clear();
+    T.max_chunk_cells = 0;
+    T.part_entries = 0;
+    T.global_frames = false;
+    for (int f = 0; f < nframes; ++f) {
+        FrameInfo& F = T.frames[f];
+        const int np = point_base[f + 1] - point_base[f];
+        const int nc = T.cell_base[f + 1] - T.cell_base[f];
+        const int k = (np + kChunkPoints - 1) / kChunkPoints;
+        F.chunk0 = (int)T.chunks.size();
+        F.nchunks = 0;
+        if (np == 0) continue;
+        if (nc > kChunkMaxCells) {
+            T.global_frames = true;
+            continue;
+        }
+        F.nchunks = k;
+        for (int c = 0; c < k; ++c) {
+            ChunkInfo C;
+            C.frame = f;
+            C.first = point_base[f] + c * kChunkPoints;
+            C.n = np - c * kChunkPoints < kChunkPoints ? np - c * kChunkPoints : kChunkPoints;
+            C.cell_base = T.cell_base[f];
+            C.ncells = nc;
+            C.part = (int)T.part_entries;
+            T.chunks.push_back(C);
+            T.part_entries += nc;
+        }
+        if (nc > T.max_chunk_cells) T.max_chunk_cells = nc;
+    }
+}
 
 }  // namespace
 
@@ -61,6 +102,7 @@ struct ppa_batch_plan_s {
     ConfigTables cfg[kNumConfigs];
     int chosen;
     size_t point_base_off;
+    size_t part_off;          // partial-count array of the chunked cell build
     size_t scratch_hist_off;  // autotuning histograms
     size_t bytes;
     bool uploaded;
@@ -130,7 +172,10 @@ void enqueue(const ppa_batch_plan* p, int ci, const float* pts, void* ws, const 
     const FrameInfo* frames = (const FrameInfo*)(base + T.frames_off);
     const int* cell_base = (const int*)(base + T.cell_base_off);
     const int* point_base = (const int*)(base + p->point_base_off);
-    launch_build_cells_batch(pts, W.pts, frames, point_base, p->nframes, T.ncells, W.status, s);
+    launch_build_cells_batch(pts, W.pts, frames, point_base, p->nframes, T.ncells,
+                             (const ChunkInfo*)(base + T.chunks_off), (int)T.chunks.size(),
+                             T.max_chunk_cells, (int*)(base + p->part_off), T.global_frames,
+                             W.status, s);
 
     PairArgs A{};
     A.cand = W.pts.local;
@@ -262,6 +307,11 @@ int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t*
         }
         T.cell_base[n_frames] = (int)cells;
         T.ncells = (int)cells;
+        make_chunks(T, p->point_base, n_frames);
+        if (T.part_entries > 0x7fffffffLL) {
+            delete p;
+            return set_error(PPA_EINVAL, "too many cells in the batch");
+        }
     }
     Workspace W{};
     layout(p, nullptr, &W);
@@ -271,9 +321,16 @@ int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t*
         off = align256(off + sizeof(FrameInfo) * (size_t)n_frames);
         p->cfg[c].cell_base_off = off;
         off = align256(off + sizeof(int) * (size_t)(n_frames + 1));
+        p->cfg[c].chunks_off = off;
+        off = align256(off + sizeof(ChunkInfo) * (p->cfg[c].chunks.size() + 1));
     }
     p->point_base_off = off;
     off = align256(off + sizeof(int) * (size_t)(n_frames + 1));
+    int64_t part = 1;
+    for (int c = 0; c < kNumConfigs; ++c)
+        part = p->cfg[c].part_entries > part ? p->cfg[c].part_entries : part;
+    p->part_off = off;
+    off = align256(off + sizeof(int) * (size_t)part);
     p->scratch_hist_off = off;
     off = align256(off + sizeof(uint64_t) * (size_t)n_frames * (size_t)bins);
     p->bytes = off;
@@ -313,6 +370,12 @@ int ppa_batch_upload(ppa_batch_plan* p, void* ws, size_t ws_bytes, hipStream_t s
                                            sizeof(int) * T.cell_base.size(),
                                            hipMemcpyHostToDevice, s),
                             "upload cell bases")))
+            return rc;
+        if (!T.chunks.empty() &&
+            (rc = hip_check(hipMemcpyAsync(base + T.chunks_off, T.chunks.data(),
+                                           sizeof(ChunkInfo) * T.chunks.size(),
+                                           hipMemcpyHostToDevice, s),
+                            "upload chunk table")))
             return rc;
     }
     if ((rc = hip_check(hipMemcpyAsync(base + p->point_base_off, p->point_base.data(),

@@ -35,13 +35,13 @@ __global__ void zero_kernel(ZeroRanges z)
 constexpr int kAssignRounds = 16;  // grouping rounds; lanes left over take an atomic each
 
 // Cell index and cell-centred local coordinates of point i, in float64;
-// cells of this box are numbered from cell_base.
-__device__ __forceinline__ void assign_point(const float* __restrict__ pts, int64_t i,
-                                             const AssignBox& B, int cell_base,
-                                             int* __restrict__ cell_of, int* __restrict__ slot,
-                                             float4* __restrict__ local,
-                                             int* __restrict__ cell_count,
-                                             unsigned* __restrict__ status)
+// cells of this box are numbered from cell_base.  Writes cell_of[i] and
+// local[i]; returns the cell.
+__device__ __forceinline__ int locate_point(const float* __restrict__ pts, int64_t i,
+                                            const AssignBox& B, int cell_base,
+                                            int* __restrict__ cell_of,
+                                            float4* __restrict__ local,
+                                            unsigned* __restrict__ status)
 {
     double p0 = (double)pts[3 * i];
     double p1 = (double)pts[3 * i + 1];
@@ -72,6 +72,18 @@ __device__ __forceinline__ void assign_point(const float* __restrict__ pts, int6
     const int cell = cell_base + (c[2] * B.ni[1] + c[1]) * B.ni[0] + c[0];
     cell_of[i] = cell;
     local[i] = make_float4((float)x, (float)y, (float)z, __int_as_float((int)i));
+    return cell;
+}
+
+// locate_point, then a slot in the cell's run from the global counters.
+__device__ __forceinline__ void assign_point(const float* __restrict__ pts, int64_t i,
+                                             const AssignBox& B, int cell_base,
+                                             int* __restrict__ cell_of, int* __restrict__ slot,
+                                             float4* __restrict__ local,
+                                             int* __restrict__ cell_count,
+                                             unsigned* __restrict__ status)
+{
+    const int cell = locate_point(pts, i, B, cell_base, cell_of, local, status);
     // A slot in the cell's run.  Lanes of the wavefront (those active here)
     // that share a cell share one atomic: inputs ordered in space put few
     // distinct cells in a wavefront, and same-address atomics serialise.
@@ -138,14 +150,81 @@ __global__ void __launch_bounds__(256) assign_batch_kernel(const float* pts, int
     if (i >= n) return;
     int f = s_f;
     while (f + 1 < nframes && point_base[f + 1] <= i) ++f;
-    // one pass per distinct frame of the wave, so each box is read uniformly
+    // one pass per distinct frame of the wave, so each box is read uniformly;
+    // the points of chunked frames are counted by assign_chunks_kernel
     for (;;) {
         const int fu = __builtin_amdgcn_readfirstlane(f);
         if (f == fu) {
-            assign_point(pts, i, frames[fu].box, frames[fu].cell_base, cell_of, slot, local,
-                         cell_count, status);
+            if (frames[fu].nchunks == 0)
+                assign_point(pts, i, frames[fu].box, frames[fu].cell_base, cell_of, slot, local,
+                             cell_count, status);
             break;
         }
+    }
+}
+
+// One chunk of one frame per workgroup: every point located, its slot inside
+// the chunk taken from the chunk's per-cell counters in LDS (two 16-bit
+// counters per word: a chunk holds at most kChunkPoints < 2^16 points, so a
+// half never carries into the other), then the counters written to the
+// chunk's row of `part`.
+__global__ void __launch_bounds__(1024) assign_chunks_kernel(const float* pts,
+                                                             const FrameInfo* __restrict__ frames,
+                                                             const ChunkInfo* __restrict__ chunks,
+                                                             int* cell_of, int* slot,
+                                                             float4* local, int* part,
+                                                             unsigned* status)
+{
+    extern __shared__ unsigned s_cnt[];
+    const ChunkInfo C = chunks[blockIdx.x];
+    const int words = (C.ncells + 1) >> 1;
+    for (int w = threadIdx.x; w < words; w += blockDim.x) s_cnt[w] = 0u;
+    __syncthreads();
+    const AssignBox& B = frames[C.frame].box;
+    for (int k = threadIdx.x; k < C.n; k += blockDim.x) {
+        const int64_t i = (int64_t)C.first + k;
+        const int j = locate_point(pts, i, B, C.cell_base, cell_of, local, status) - C.cell_base;
+        const unsigned sh = (unsigned)(j & 1) << 4;
+        const unsigned old = atomicAdd(&s_cnt[j >> 1], 1u << sh);
+        slot[i] = (int)((old >> sh) & 0xffffu);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < C.ncells; j += blockDim.x)
+        part[C.part + j] = (int)((s_cnt[j >> 1] >> ((unsigned)(j & 1) << 4)) & 0xffffu);
+}
+
+// Per chunk, after every chunk of the batch has counted: the chunk's first
+// slot in each cell of its frame (the sum of the earlier chunks' counts
+// there, in LDS), the frame's cell counts (by its last chunk), and each of
+// its points' slot made final (first slot + slot inside the chunk).
+__global__ void __launch_bounds__(1024) chunk_finish_kernel(const FrameInfo* __restrict__ frames,
+                                                            const ChunkInfo* __restrict__ chunks,
+                                                            const int* __restrict__ part,
+                                                            const int* __restrict__ cell_of,
+                                                            int* slot, int* cell_count)
+{
+    extern __shared__ int s_first[];
+    const int k = blockIdx.x;
+    const ChunkInfo C = chunks[k];
+    const int k0 = frames[C.frame].chunk0;
+    const bool last = k == k0 + frames[C.frame].nchunks - 1;
+    // the earlier chunks' rows follow each other in `part` (ncells apart)
+    const int* rows = part + chunks[k0].part;
+    const int nrows = k - k0;
+    for (int j = threadIdx.x; j < C.ncells; j += blockDim.x) {
+        int b = 0;
+        int q = 0;
+        for (; q + 4 <= nrows; q += 4)  // four independent loads in flight
+            b += rows[(size_t)q * C.ncells + j] + rows[(size_t)(q + 1) * C.ncells + j] +
+                 rows[(size_t)(q + 2) * C.ncells + j] + rows[(size_t)(q + 3) * C.ncells + j];
+        for (; q < nrows; ++q) b += rows[(size_t)q * C.ncells + j];
+        s_first[j] = b;
+        if (last) cell_count[C.cell_base + j] = b + part[C.part + j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < C.n; t += blockDim.x) {
+        const int64_t i = (int64_t)C.first + t;
+        slot[i] += s_first[cell_of[i] - C.cell_base];
     }
 }
 
@@ -452,16 +531,36 @@ void launch_build_cells(const float* pts, CellList& cl, const BoxPrep& b, const 
 }
 
 void launch_build_cells_batch(const float* pts, CellList& cl, const FrameInfo* frames,
-                              const int* point_base, int nframes, int ncells, unsigned* status,
-                              hipStream_t s)
+                              const int* point_base, int nframes,
+                              int ncells, const ChunkInfo* chunks, int nchunks, int max_chunk_cells,
+                              int* part, bool global_frames, unsigned* status, hipStream_t s)
 {
     const int64_t n = cl.n;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    if (n > 0)
+    if (n > 0 && global_frames)
         hipLaunchKernelGGL(assign_batch_kernel, dim3(blocks), dim3(256), 0, s, pts, n, frames,
                            point_base, nframes, cl.cell_of, cl.slot, cl.local, cl.cell_count,
                            status);
-    finish_cells(cl, ncells, s);
+    if (nchunks > 0) {
+        const size_t lds = sizeof(unsigned) * (size_t)((max_chunk_cells + 1) / 2);
+        (void)hipFuncSetAttribute((const void*)assign_chunks_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(assign_chunks_kernel, dim3((unsigned)nchunks), dim3(1024), lds, s, pts,
+                           frames, chunks, cl.cell_of, cl.slot, cl.local, part, status);
+        const size_t lds2 = sizeof(int) * (size_t)max_chunk_cells;
+        (void)hipFuncSetAttribute((const void*)chunk_finish_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+        hipLaunchKernelGGL(chunk_finish_kernel, dim3((unsigned)nchunks), dim3(1024), lds2, s,
+                           frames, chunks, part, cl.cell_of, cl.slot, cl.cell_count);
+    }
+    launch_scan<int>(cl.cell_count, cl.cell_start, ncells, cl.scan_flags, cl.scan_ticket, nullptr,
+                     s);
+    if (n > 0) {
+        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of, cl.slot,
+                           cl.local, cl.cell_start, cl.sorted);
+        hipLaunchKernelGGL(rank_kernel, dim3(blocks), dim3(256), 0, s, n, cl.cell_of,
+                           cl.cell_start, cl.sorted, cl.local);
+    }
 }
 
 }  // namespace ppa

@@ -82,8 +82,30 @@ struct FrameInfo {
     int nsten;             // 27 in 3D, 9 in 2D
     int dot;               // expanded in/out test allowed for this frame's cells
     int point_base;        // first global point index of the frame
+    int chunk0, nchunks;   // its chunks in the chunk table (nchunks 0: global counters)
     float off[27][4];      // stencil offsets M (delta / n), float32
 };
+
+// The batch cell build counts the points of a frame per cell in LDS, one
+// workgroup per chunk of at most kChunkPoints consecutive points of one
+// frame, instead of with global atomics (one per point, on cells in random
+// order when the points are): each chunk writes its per-cell counts to its
+// own row of a partial-count array; then each chunk sums the rows of the
+// frame's earlier chunks into its first slot in every cell, and a point's
+// slot in its cell is that plus its slot inside the chunk.  Frames with
+// more than kChunkMaxCells cells (counted as 16-bit halves of 32-bit LDS
+// words; the first slots take 4 bytes a cell of LDS) use the global
+// counters.
+struct ChunkInfo {
+    int frame;
+    int first;      // first point
+    int n;          // points
+    int cell_base;  // the frame's first cell
+    int ncells;     // the frame's cells
+    int part;       // first entry of this chunk's row in the partial-count array
+};
+constexpr int kChunkPoints = 16384;
+constexpr int kChunkMaxCells = 32768;
 
 // Per-workgroup partial arrays are summed in two stages; the first sums
 // kPartialRowsPer of them at a time into one row of first-stage sums.
@@ -109,9 +131,13 @@ void launch_scan_i64_total(const int* in, int64_t* out, int64_t n, unsigned long
                            int* ticket, unsigned long long* total, hipStream_t s);
 size_t scan_flag_count(int64_t n);
 // Batch: cells of every frame in one global list (cells.hip).
+// chunks: the chunk table ([nchunks], device); part: the partial-count
+// array its rows index; global_frames: whether any frame uses the global
+// counters.
 void launch_build_cells_batch(const float* pts, CellList& cl, const FrameInfo* frames,
-                              const int* point_base, int nframes, int ncells, unsigned* status,
-                              hipStream_t s);
+                              const int* point_base, int nframes,
+                              int ncells, const ChunkInfo* chunks, int nchunks, int max_chunk_cells,
+                              int* part, bool global_frames, unsigned* status, hipStream_t s);
 bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r);
 int check_cutoff(const BoxPrep& bp, double r);
 
