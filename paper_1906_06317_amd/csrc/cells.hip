@@ -245,8 +245,14 @@ __global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int* __re
 // run with a smaller index (its rank) and moves there.  The runs a
 // workgroup's entries belong to are contiguous (the entries are sorted by
 // cell), so their indices are staged in LDS once and every count reads LDS;
-// runs spanning more than kRankSpan entries read global memory instead.
+// runs spanning more than kRankSpan entries read global memory instead.  An
+// entry's cell is found by binary search in the workgroup's slice of the
+// cell starts, also staged in LDS, rather than read through the point's
+// index (a read at a random place when the points are in random order:
+// the 256-frame batch 175 -> 130 us); slices of more than kRankCells cells
+// (long runs of empty cells) read it through the index.
 constexpr int kRankSpan = 2048;
+constexpr int kRankCells = 512;
 
 __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restrict__ cell_of,
                                                    const int* __restrict__ cell_start,
@@ -254,16 +260,23 @@ __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restr
                                                    float4* __restrict__ out)
 {
     __shared__ int s_id[kRankSpan];
-    __shared__ int s_lo, s_hi;
+    __shared__ int s_cs[kRankCells + 1];
+    __shared__ int s_c0, s_c1;
     const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t p = p0 + threadIdx.x;
     if (threadIdx.x == 0) {
         const int64_t last = p0 + blockDim.x - 1 < n ? p0 + blockDim.x - 1 : n - 1;
-        s_lo = cell_start[cell_of[__float_as_int(in[p0].w)]];
-        s_hi = cell_start[cell_of[__float_as_int(in[last].w)] + 1];
+        s_c0 = cell_of[__float_as_int(in[p0].w)];
+        s_c1 = cell_of[__float_as_int(in[last].w)];
     }
     __syncthreads();
-    const int lo = s_lo, hi = s_hi;
+    const int c0 = s_c0, c1 = s_c1;
+    const bool cells_staged = c1 - c0 < kRankCells;
+    if (cells_staged)
+        for (int k = threadIdx.x; k <= c1 - c0 + 1; k += blockDim.x) s_cs[k] = cell_start[c0 + k];
+    __syncthreads();
+    const int lo = cells_staged ? s_cs[0] : cell_start[c0];
+    const int hi = cells_staged ? s_cs[c1 - c0 + 1] : cell_start[c1 + 1];
     const bool staged = hi - lo <= kRankSpan;
     if (staged)
         for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x)
@@ -272,8 +285,20 @@ __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restr
     if (p >= n) return;
     const float4 v = in[p];
     const int id = __float_as_int(v.w);
-    const int c = cell_of[id];
-    const int b = cell_start[c], e = cell_start[c + 1];
+    int b, e;
+    if (cells_staged) {
+        // the last cell of the slice starting at or before p holds it (empty
+        // cells before it start at the same place)
+        int k = 0;
+        for (int step = kRankCells; step > 0; step >>= 1)
+            if (k + step <= c1 - c0 && s_cs[k + step] <= p) k += step;
+        b = s_cs[k];
+        e = s_cs[k + 1];
+    } else {
+        const int c = cell_of[id];
+        b = cell_start[c];
+        e = cell_start[c + 1];
+    }
     int r = 0;
     if (staged) {
         for (int j = b; j < e; ++j) r += s_id[j - lo] < id;
