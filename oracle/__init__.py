@@ -1,6 +1,6 @@
 """FP64 reference oracle (test infrastructure only).
 
-This package is the checker that the GPU library is graded against.  Only
+This package is the reference that the GPU library is checked against.  Only
 the test suite, the smoke check and the CPU-baseline leg of the benchmark
 import it; the GPU library never does, and the two share no code.
 

@@ -4,8 +4,8 @@
  * correlation function of per-particle values, and a Gaussian-smoothed RDF
  * with its gradient.
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
- * graded against.  Only the test suite, the smoke check and the CPU-baseline
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark load it.  It shares no code, header or constant with
  * the GPU library, and the GPU library never calls it.
  *
