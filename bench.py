@@ -372,6 +372,7 @@ def paper_context(ppa):
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 # v_exp_f32 is a quarter-rate transcendental: 16 lanes per CU per clock.
 EXP_PEAK = 256 * 16 * 2.4e9
+ADJOINT_TERM_OPS = 7
 
 
 def valu_diagnostic(ppa, box, n, r_max, count_ms, fill_ms):
@@ -743,9 +744,17 @@ def row_smooth(ppa, hip):
             "roofline": {"bound": "alu", "unit": "exp/s", "peak": EXP_PEAK,
                          "forward_achieved": terms / (fwd_ms * 1e-3),
                          "forward_frac": terms / (fwd_ms * 1e-3) / EXP_PEAK,
-                         "adjoint_achieved": terms / (bwd_ms * 1e-3),
-                         "adjoint_frac": terms / (bwd_ms * 1e-3) / EXP_PEAK,
-                         "note": "one exp2 per window term (quarter-rate transcendental peak)"}}
+                         "note": "forward: one exp2 per window term (quarter-rate "
+                                 "transcendental peak)",
+                         "adjoint": {"bound": "alu", "unit": "lane-op/s",
+                                     "peak": VALU_LANE_OPS, "ops_per_term": ADJOINT_TERM_OPS,
+                                     "achieved": ADJOINT_TERM_OPS * terms / (bwd_ms * 1e-3),
+                                     "frac": ADJOINT_TERM_OPS * terms / (bwd_ms * 1e-3)
+                                     / VALU_LANE_OPS,
+                                     "note": "adjoint: Gaussians by recurrence, 7 lane "
+                                             "operations per window term (4 float32 "
+                                             "multiplies, an add, a conversion and a "
+                                             "float64 add)"}}}
 
 
 def _cpu_model():

@@ -936,6 +936,8 @@ int run_smooth(const ppa_box* box, const float* pts, int64_t n, int32_t bins, fl
     A.inv_dr = (float)((double)bins / (double)r_max);
     const double sg = sigma;
     A.k2 = (float)(1.4426950408889634 / (2.0 * sg * sg));
+    const double drf = (double)(float)A.dr;  // the step the kernel adds
+    A.step2 = (float)exp2(-2.0 * (double)A.k2 * drf * drf);
     A.hscale = (float)(A.dr / (sg * sqrt(2.0 * M_PI)));
     A.gscale = (float)(A.dr / (sg * sg * sg * sqrt(2.0 * M_PI)));
     A.partial = partial;

@@ -394,6 +394,7 @@ struct SmoothArgs {
     double w8;                // window half-width 8 sigma
     float inv_dr;             // bins / r_max
     float k2;                 // log2(e) / (2 sigma^2)
+    float step2;              // 2^(-2 k2 dr^2): ratio of consecutive bins' Gaussian factors
     float hscale;             // dr / (sigma sqrt(2 pi)): forward weight of exp(-u^2/2s^2)
     float gscale;             // dr / (sigma^3 sqrt(2 pi)): adjoint weight of u exp(-u^2/2s^2)
     int split;                // work units per home cell (its queries in parts)

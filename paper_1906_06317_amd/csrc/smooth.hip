@@ -178,16 +178,25 @@ __device__ __forceinline__ void flush_bwd(const SmoothArgs& a, const SmoothShare
             int b0, b1;
             float u0;
             window(a, r, b0, b1, u0);
-            // the window's terms change sign with u: sum them in float64;
-            // the walk starts at a lane-dependent bin (fewer LDS conflicts)
+            // the window's terms change sign with u: sum them in float64.
+            // Consecutive bins' Gaussians by recurrence: with u' = u + dr,
+            // e(u') = e(u) p(u) and p(u') = p(u) c, where p(u) =
+            // 2^(-k2 (2 u dr + dr^2)) and c = 2^(-2 k2 dr^2); two exp2 per
+            // pair instead of one per bin (relative error of a term after
+            // the window's ~20 steps: a few 1e-6)
             double A = 0.0;
             const int nb = b1 - b0 + 1;
-            int m = nb > 0 ? lane % nb : 0;
+            float u = u0;
+            float e = __builtin_amdgcn_exp2f(-(u * u) * a.k2);
+            float p = __builtin_amdgcn_exp2f(-a.k2 * drf * fmaf(2.f, u, drf));
+            const float c = a.step2;
+            const float* g = G + b0;
 #pragma unroll 4
             for (int j = 0; j < nb; ++j) {
-                const float u = fmaf((float)m, drf, u0);
-                A += (double)(G[b0 + m] * u * __builtin_amdgcn_exp2f(-(u * u) * a.k2));
-                m = m + 1 == nb ? 0 : m + 1;
+                A += (double)(g[j] * u * e);
+                e *= p;
+                p *= c;
+                u += drf;
             }
             const double f = -2.0 * A / r;
             ax = fma(f, dx, ax);
