@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "internal.hpp"
@@ -222,6 +223,27 @@ bool expanded_test_ok(const BoxPrep& bp, const Grid& g, double r)
     const double err = u * (3 * cmax * cmax + 3 * (cmax * cmax + 2 * cmax * qmax) +
                             3 * qmax * qmax + (r * r + qmax * qmax));
     return err <= 0.5e-5 * r * r;
+}
+
+int device_cus()
+{
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> cache[kMaxDevices];  // 0: not queried yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+    if (dev >= kMaxDevices) {
+        hipDeviceProp_t prop;
+        return hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 256;
+    }
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        hipDeviceProp_t prop;
+        v = hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0
+                ? prop.multiProcessorCount
+                : 256;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 // Wavefronts sharing each home cell's queries in the ball query's passes.

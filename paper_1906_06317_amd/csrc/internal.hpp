@@ -189,6 +189,10 @@ void launch_fill_batch(const PairArgs& a, const BatchGeom& b, int dim, int excl,
 
 // excl: 0 keep i == j, 1 points query themselves (drop the query's own
 // entry), 2 separate query points (drop j == i by index).
+// Compute units of the current device (queried once per device; 256 if the
+// query fails).  Safe to call from several host threads.
+int device_cus();
+
 void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s);
 void launch_fill(const PairArgs& a, int dim, int excl, bool nl, bool hist, hipStream_t s);
 // Orders every complete row of a CSR list by neighbour index (distances follow).

@@ -218,14 +218,7 @@ void launch_zero_words(unsigned* p, long long words, hipStream_t s)
 
 int knn_list_workgroups(long long nq)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     // a few rows per wavefront keep the threshold guess warm; many
     // wavefronts hide the latency of each row's loads
     long long want = (nq + 4LL * kKlWaves - 1) / (4LL * kKlWaves);

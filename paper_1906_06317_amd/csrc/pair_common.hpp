@@ -446,14 +446,7 @@ __global__ void __launch_bounds__(256) partial_sum_stage1(const T* __restrict__ 
 template <typename K>
 inline int resident_blocks(K kernel, size_t lds, long long ncells)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess ||
         per_cu < 1)

@@ -882,14 +882,7 @@ void launch_count(const PairArgs& a, int dim, int excl, hipStream_t s)
 template <typename K>
 static int batch_blocks(K kernel, int threads, size_t lds, int blocks_cap)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
         per_cu < 1)

@@ -205,14 +205,7 @@ __global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __rest
 // fills most of the LDS), or of the global-atomics launch; a multiple of 8.
 int pmft_workgroups(int words)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     const size_t lds = sizeof(unsigned) * (size_t)words;
     int per_cu = 0;
     hipError_t e = words > 0
@@ -226,17 +219,17 @@ int pmft_workgroups(int words)
 
 size_t pmft_lds_limit()
 {
-    static size_t limit = 0;
-    if (limit == 0) {
+    // initialised once, thread-safely
+    static const size_t limit = [] {
         int dev = 0, v = 0;
-        limit = 65536;
+        size_t l = 65536;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             v > 0)
-            limit = (size_t)v;
+            l = (size_t)v;
         // the static part of the kernel's LDS
-        limit -= sizeof(PmftLds) + sizeof(float2) * kBondBuf * kPmftWaves + 256;
-    }
+        return l - (sizeof(PmftLds) + sizeof(float2) * kBondBuf * kPmftWaves + 256);
+    }();
     return limit;
 }
 

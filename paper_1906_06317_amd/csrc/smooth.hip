@@ -310,14 +310,7 @@ __global__ void __launch_bounds__(256) smooth_reduce_kernel(const double* __rest
 template <int DIM, bool BWD>
 int occupancy_blocks(size_t dyn)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, smooth_kernel<DIM, BWD>, kBlock,
                                                      dyn) != hipSuccess ||

@@ -125,14 +125,7 @@ void launch_sort_rows(const int64_t* offsets, int64_t nq, int32_t* idx, float* d
                       int64_t capacity, hipStream_t s)
 {
     if (nq <= 0 || !idx) return;
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                  ? prop.multiProcessorCount
-                  : 256;
-    }
+    const int cus = device_cus();
     long long blocks = (nq + kSortWaves - 1) / kSortWaves;
     const long long cap = 16LL * cus;
     if (blocks > cap) blocks = cap;
