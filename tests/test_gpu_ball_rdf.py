@@ -116,6 +116,42 @@ def test_separate_query_points(ppa):
         check_hist(c, lo, hi)
 
 
+@pytest.mark.parametrize("frac", [0.32, 0.62])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_few_full_cells_split_among_wavefronts(ppa, dim, frac):
+    """Few cells holding many queries each (a cutoff large against the box):
+    the count and fill passes share each cell's queries among several
+    wavefronts.  Self queries (the own entry found by its position in the
+    home cell, beyond the first 64 too), separate query points with and
+    without dropping equal indices, and the RDF of the same passes."""
+    rng = np.random.default_rng(11 + dim)
+    n = 3000
+    s = workloads.uniform(n, 2.0, seed=12 + dim, dim=dim, tilt=(0.2, 0.1, -0.1) if dim == 3
+                          else (0.2, 0.0, 0.0))
+    half = 0.5 * brute.perpendicular_widths(tuple(s.L), tuple(s.tilt), dim)[:dim].min()
+    # six cells per axis (candidates in register slots) or three (every
+    # point a candidate, and home cells of more than 64 points)
+    r_max = float(frac * half)
+    box = _box(s)
+    ob = oracle.make_box(s.L, s.tilt, dim)
+    nl = ppa.query_ball(box, s.points, r_max)
+    check_rows(nl, _oracle_all(s, r_max), range(n), r_max)
+    A = workloads.lattice_vectors(s.L, s.tilt, dim)
+    nq = 5000
+    f = rng.uniform(-0.5, 0.5, (nq, 3))
+    if dim == 2:
+        f[:, 2] = 0.0
+    q = (f @ A.T).astype(np.float32)
+    q[:200] = s.points[:200]  # some queries coincide with points
+    for excl in (False, True):
+        nl = ppa.query_ball(box, s.points, r_max, query_points=q, exclude_ii=excl)
+        ref = oracle.ball_query(ob, s.points, r_max, query_points=q, exclude_ii=excl)
+        check_rows(nl, ref, range(nq), r_max)
+        c = ppa.rdf_counts(box, s.points, 64, r_max, query_points=q, exclude_ii=excl).cpu().numpy()
+        lo, hi, _ = oracle.rdf_counts(ob, s.points, 64, r_max, query_points=q, exclude_ii=excl)
+        check_hist(c, lo, hi)
+
+
 def test_self_pairs_and_coincident_points(ppa):
     pts = np.zeros((5, 3), np.float32)
     pts[3] = [1.0, 0, 0]
