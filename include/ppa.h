@@ -568,6 +568,15 @@ int ppa_batch_config(ppa_batch_plan* plan, int32_t index, int32_t* n_configs, in
 int ppa_batch_config_shape(ppa_batch_plan* plan, int32_t index, int32_t* cells_per_item,
                            int32_t* waves_per_workgroup);
 
+/* Cell grid of configuration `index` (-1: the chosen one) as the cell build
+ * sees it: the cells of all frames, and how they are counted.  Frames with
+ * at most 32768 cells are counted per chunk of 16384 points in LDS
+ * (`chunks`: the number of such chunks over all frames); the others with
+ * one global atomic per point (`global_frames`: their number).  Any pointer
+ * may be NULL.  Host only. */
+int ppa_batch_config_cells(ppa_batch_plan* plan, int32_t index, int32_t* cells, int32_t* chunks,
+                           int32_t* global_frames);
+
 /* Autotuner: runs every configuration (one warm-up and `reps` timed runs,
  * HIP events on the stream, which it synchronizes) and selects the fastest
  * for later runs and graphs.  The NeighborList arguments are used as

@@ -138,6 +138,7 @@ def lib():
             "ppa_batch_run": [P, P, P, sz, P, P, P, P, P, i64, P, P],
             "ppa_batch_config": [P, i32, P, P, P, P],
             "ppa_batch_config_shape": [P, i32, P, P],
+            "ppa_batch_config_cells": [P, i32, P, P, P],
             "ppa_batch_autotune": [P, P, P, sz, P, P, P, P, i64, P, i32, P, P],
             "ppa_batch_graph_create": [P, P, P, sz, P, P, P, P, P, i64, P,
                                        ctypes.POINTER(ctypes.c_void_p)],
@@ -935,6 +936,14 @@ class BatchPlan:
         return {"n_configs": n.value, "chosen": c.value, "cell_scale": scale.value,
                 "blocks_per_cu": cap.value, "cells_per_item": run.value,
                 "waves_per_workgroup": waves.value}
+
+    def cells(self, index=-1):
+        """Cell build of a configuration (-1: the chosen one): total cells,
+        LDS-counted chunks, and frames counted with global atomics."""
+        c, k, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ppa_batch_config_cells(self._h, int(index), ctypes.byref(c), ctypes.byref(k),
+                                            ctypes.byref(g)))
+        return {"cells": c.value, "chunks": k.value, "global_frames": g.value}
 
     def autotune(self, points, reps=3, stream=None):
         """Times every launch configuration on these points and keeps the fastest."""

@@ -427,6 +427,23 @@ int ppa_batch_config_shape(ppa_batch_plan* p, int32_t index, int32_t* cells_per_
     return PPA_OK;
 }
 
+int ppa_batch_config_cells(ppa_batch_plan* p, int32_t index, int32_t* cells, int32_t* chunks,
+                           int32_t* global_frames)
+{
+    if (!p) return set_error(PPA_EINVAL, "plan is NULL");
+    if (index >= kNumConfigs) return set_error(PPA_EINVAL, "no configuration %d", index);
+    const ConfigTables& T = p->cfg[index >= 0 ? index : p->chosen];
+    if (cells) *cells = T.ncells;
+    if (chunks) *chunks = (int32_t)T.chunks.size();
+    if (global_frames) {
+        int g = 0;
+        for (int f = 0; f < p->nframes; ++f)
+            if (T.frames[f].nchunks == 0 && p->point_base[f + 1] > p->point_base[f]) ++g;
+        *global_frames = g;
+    }
+    return PPA_OK;
+}
+
 int ppa_batch_autotune(ppa_batch_plan* p, const float* pts, void* ws, size_t ws_bytes,
                        int64_t* offsets, int32_t* counts, int32_t* point_idx, float* dist,
                        int64_t capacity, int64_t* n_pairs_dev, int32_t reps, hipStream_t s,

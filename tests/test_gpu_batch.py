@@ -84,6 +84,43 @@ def test_small_trajectory_against_oracle_and_per_frame_calls(ppa):
         np.testing.assert_array_equal(pidx[off[pb[f]]:off[pb[f + 1]]], fnl.point_idx.cpu().numpy())
 
 
+def test_cell_build_chunks_and_global_counters(ppa):
+    """A batch whose frames take both cell-build paths: a frame with more
+    cells than a chunk counts in LDS (global counters), a frame of several
+    chunks, and small frames; every frame's rows and bins against the
+    oracle, with the graph's replay equal to the run."""
+    import torch
+    r_max, bins = 0.6, 32
+    # (points, density, tilts): the sparse frame has far more than 32768
+    # cells, the dense 40000-point frame fewer, in three chunks
+    specs = [(40000, 0.05, (0.1, -0.2, 0.05)), (40000, 8.0, (0.0, 0.1, 0.0)),
+             (3000, 1.0, (0.2, 0.0, -0.1)), (500, 1.0, (0.0, 0.0, 0.0)),
+             (17000, 0.5, (-0.1, 0.1, 0.2))]
+    frames = [workloads.uniform(n, rho, seed=300 + k, tilt=t)
+              for k, (n, rho, t) in enumerate(specs)]
+    boxes = [ppa.Box(f.L, f.tilt, f.dim) for f in frames]
+    sizes = [f.points.shape[0] for f in frames]
+    plan = ppa.BatchPlan(boxes, sizes, bins, r_max)
+    cells = plan.cells()
+    assert cells["global_frames"] == 1, cells  # the sparse frame
+    assert cells["chunks"] == 3 + 1 + 1 + 2, cells  # 40000 and 17000 points: several chunks
+    pts = torch.as_tensor(np.concatenate([f.points for f in frames])).cuda()
+    hist, nl = plan.run(pts)
+    h = hist.cpu().numpy()
+    pb = plan.offsets_host
+    for f, s in enumerate(frames):
+        ob = oracle.make_box(s.L, s.tilt, s.dim)
+        lo, hi, _ = oracle.rdf_counts(ob, s.points, bins, r_max)
+        check_hist(h[f], lo, hi)
+        ref = oracle.ball_query(ob, s.points, r_max)
+        check_rows(_FrameNL(nl, pb[f], pb[f + 1]), ref, range(s.points.shape[0]), r_max)
+    h2 = torch.zeros_like(hist)
+    launch = plan.graph(pts, h2)
+    launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(h2.cpu().numpy(), h)
+
+
 def test_every_configuration_and_the_autotuner(ppa):
     frames = _frames(12, 6, 2000, 8000)
     plan, pts = _plan(ppa, frames)

@@ -264,3 +264,31 @@ def test_cluster_flags_and_workspace_errors():
     assert args(2, ctypes.c_void_p(4096)) == ppa.PPA_EINVAL          # unknown flag
     assert args(ppa.PPA_CLUSTER_SYMMETRIC, None) == ppa.PPA_EWORKSPACE  # flag accepted
     assert args(0, ctypes.c_void_p(4096 + 8)) == ppa.PPA_EWORKSPACE  # misaligned
+
+
+def test_batch_cell_build_chunking():
+    """The batch plan splits frames of at most 32768 cells into chunks of
+    16384 points counted in LDS and leaves larger frames to global counters
+    (host logic of plan creation; no device work)."""
+    from paper_1906_06317_amd import workloads
+    L = ppa.lib()
+    specs = [(40000, 0.05), (40000, 8.0), (3000, 1.0), (0, 1.0), (500, 1.0), (17000, 0.5)]
+    # (the empty frame takes the box of 1000 points)
+    frames = [workloads.uniform(n or 1000, rho, seed=300 + k) for k, (n, rho) in enumerate(specs)]
+    boxes = (ppa.CBox * len(frames))(*[ppa.Box(f.L, f.tilt, 3).c() for f in frames])
+    off = np.concatenate([[0], np.cumsum([n for n, _ in specs])]).astype(np.int64)
+    h = ctypes.c_void_p()
+    assert L.ppa_batch_plan_create(len(frames), boxes, off.ctypes.data_as(ctypes.c_void_p), 32,
+                                   0.0, 0.6, 1, 0, ctypes.byref(h)) == 0
+    try:
+        c, k, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        for index in (-1, 0):
+            assert L.ppa_batch_config_cells(h, index, ctypes.byref(c), ctypes.byref(k),
+                                            ctypes.byref(g)) == 0
+            # 40000 points in 3 chunks, 3000 and 500 in one each, 17000 in 2; the
+            # empty frame has none; the sparse frame has more than 32768 cells
+            assert (k.value, g.value) == (7, 1)
+            assert c.value > 32768
+        assert L.ppa_batch_config_cells(h, 99, None, None, None) == ppa.PPA_EINVAL
+    finally:
+        L.ppa_batch_plan_destroy(h)
