@@ -317,11 +317,13 @@ __global__ void __launch_bounds__(256) rank_kernel(int64_t n, const int* __restr
 // 2 inclusive prefix) and the value in the low 62.
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
-// items per thread: 2 for short arrays (many tiles in flight), 16 for long
-// ones (a tile of 16384 items per workgroup, read and written as 16-byte
-// vectors; 2^20 items make 64 tiles, a look-back of one window).  Against 4
-// items per thread: 2^20 row counts 15.0 -> 11.0 us, 1.1e7 (a 256-frame
-// batch) 146 -> 87 us.
+// items per thread: 2 for short arrays (many tiles in flight), 4 from
+// 131,072 items and 16 from 2^20 (tiles of 4096 and 16384 items per
+// workgroup, read and written as 16-byte vectors; 2^20 items make 64 tiles
+// of 16384, a look-back of one window).  Against 4 items per thread, 16
+// took 2^20 row counts 15.0 -> 11.0 us and 1.1e7 (a 256-frame batch)
+// 146 -> 87 us, but 2.4e5 cell counts (the k-NN grid) 5.5 -> 7.4 us: too
+// few tiles to fill the CUs.
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
@@ -451,8 +453,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const int* __restric
 }  // namespace
 
 constexpr int kSmallItems = 2;
+constexpr int kMidItems = 4;
 constexpr int kLargeItems = 16;
 constexpr int64_t kLargeFrom = 64LL * kScanThreads * kSmallItems;
+constexpr int64_t kHugeFrom = 64LL * kScanThreads * kLargeItems;  // 2^20: 64 tiles of 16384
 
 // Status words the scan of n items needs (one per tile of the small size).
 size_t scan_flag_count(int64_t n)
@@ -470,6 +474,11 @@ static void launch_scan(const int* in, Out* out, int64_t n, unsigned long long* 
         const int64_t tile = (int64_t)kScanThreads * kSmallItems;
         const int64_t tiles = n > 0 ? (n + tile - 1) / tile : 1;
         hipLaunchKernelGGL((scan_kernel<Out, kSmallItems>), dim3((unsigned)tiles),
+                           dim3(kScanThreads), 0, s, in, out, n, flags, ticket, total);
+    } else if (n < kHugeFrom) {
+        const int64_t tile = (int64_t)kScanThreads * kMidItems;
+        const int64_t tiles = (n + tile - 1) / tile;
+        hipLaunchKernelGGL((scan_kernel<Out, kMidItems>), dim3((unsigned)tiles),
                            dim3(kScanThreads), 0, s, in, out, n, flags, ticket, total);
     } else {
         const int64_t tile = (int64_t)kScanThreads * kLargeItems;
