@@ -31,13 +31,14 @@ __device__ __forceinline__ float lane_off(float v, int t)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
 }
 
-// v with lane t replaced by the uniform value x (one v_writelane; the lane
-// select goes through M0, as the instruction reads at most one other SGPR).
-__device__ __forceinline__ int with_lane(int v, int t, int x)
-{
-    asm("v_writelane_b32 %0, %1, m0" : "=v"(v) : "s"(x), "{m0}"(t), "0"(v));
-    return v;
-}
+// The writelane intrinsic, called directly rather than written as inline
+// assembly, so the compiler sees the instruction and inserts the wait
+// states it needs (a v_writelane reading an SGPR that a vector instruction
+// has just written can otherwise see the old value).
+__device__ int amdgcn_writelane(int x, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// v with lane t replaced by the uniform value x (one v_writelane).
+__device__ __forceinline__ int with_lane(int v, int t, int x) { return amdgcn_writelane(x, t, v); }
 
 __device__ __forceinline__ long long lane_of64(long long v, int t)
 {
