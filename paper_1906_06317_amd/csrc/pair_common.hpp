@@ -17,6 +17,14 @@ __device__ __forceinline__ unsigned lane_prefix(unsigned long long mask)
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// base + the number of set bits of mask below this lane (the running count
+// rides in the mbcnt addend, so no separate add is needed).
+__device__ __forceinline__ int lane_slot(unsigned long long mask, int base)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)base));
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ float uniformf(float v)
@@ -39,6 +47,13 @@ __device__ int amdgcn_writelane(int x, int lane, int old) __asm("llvm.amdgcn.wri
 
 // v with lane t replaced by the uniform value x (one v_writelane).
 __device__ __forceinline__ int with_lane(int v, int t, int x) { return amdgcn_writelane(x, t, v); }
+
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 __device__ __forceinline__ long long lane_of64(long long v, int t)
 {

@@ -285,15 +285,24 @@ struct Filler {
     {
     }
 
+    __device__ __forceinline__ void bin_at(float t)
+    {
+        const int b = min((int)t, O.bins - 1);
+        if (hist_lds)
+            atomicAdd(&hist_lds[b], 1u);
+        else
+            atomicAdd(&ghist[b], 1ull);
+    }
     __device__ __forceinline__ void bin(float r)
     {
-        const float t = (r - O.r_min) * O.inv_dr;
-        if (t >= 0.f && t < (float)O.bins) {
-            const int b = min((int)t, O.bins - 1);
-            if (hist_lds)
-                atomicAdd(&hist_lds[b], 1u);
-            else
-                atomicAdd(&ghist[b], 1ull);
+        if (O.r_min == 0.f) {
+            // r >= 0, and r - 0 is r: the same t without the subtraction or
+            // the lower test
+            const float t = r * O.inv_dr;
+            if (t < (float)O.bins) bin_at(t);
+        } else {
+            const float t = (r - O.r_min) * O.inv_dr;
+            if (t >= 0.f && t < (float)O.bins) bin_at(t);
         }
     }
     __device__ __forceinline__ void emit(long long dst, int id, float r)
@@ -330,15 +339,23 @@ struct Filler {
         if constexpr (NL) {
             int before = 0;  // row starts in earlier 64-hit blocks
             for (int e0 = 0; e0 < nh; e0 += kWave) {
-                const unsigned long long bm = W.starts[e0 >> 6];
+                const unsigned long long bm = uniform64(W.starts[e0 >> 6]);
                 const int e = e0 + lane;
-                const int r = before + (int)lane_prefix(bm) + (int)((bm >> lane) & 1ull) - 1;
+                // starts at hits e0 .. e: those at bits 1 .. lane counted by
+                // the mbcnt of bm >> 1, plus bit 0
+                const int r = lane_slot(bm >> 1, before + (int)(bm & 1ull) - 1);
                 before += __popcll(bm);
                 if (e < nh) {
+                    // the three reads depend only on e and r: issue them together
                     const float4 h = W.hit[e];
                     const float4 q = W.rq[r];
+                    const long long b = W.base[r];
+                    // keep the index with the rest of the record's read (one
+                    // 16-byte read, not a second one in the store branch)
+                    int id = __float_as_int(h.w);
+                    asm volatile("" : "+v"(id));
                     const float d = fast_sqrt(dist2<DIM>(h.x - q.x, h.y - q.y, h.z - q.z));
-                    emit(W.base[r] + e, __float_as_int(h.w), d);
+                    emit(b + e, id, d);
                     if (HIST) bin(d);
                 }
             }
