@@ -98,6 +98,15 @@ def test_random_triclinic_boxes(ppa, dim, seed):
         lo, hi, amb = oracle.rdf_counts(oracle.make_box(s.L, s.tilt, dim), s.points, bins, r_max,
                                         r_min)
         check_hist(c, lo, hi)
+        # the same bins from the pass that also writes the list (r_min > 0
+        # and r_min = 0 take different binning code there)
+        for rm in (r_min, 0.0):
+            c2, nl2 = ppa.rdf_counts(box, s.points, bins, r_max, r_min=rm, neighbor_list=True)
+            if rm == 0.0:
+                lo, hi, amb = oracle.rdf_counts(oracle.make_box(s.L, s.tilt, dim), s.points, bins,
+                                                r_max, 0.0)
+            check_hist(c2.cpu().numpy(), lo, hi)
+            assert int(nl2.n_pairs) == int(nl.n_pairs)
 
 
 def test_separate_query_points(ppa):
