@@ -54,6 +54,10 @@ struct ConfigTables {
 // Splits the frames into chunks for the cell build: each frame with at most
 // kChunkMaxCells cells gets ceil(points / kChunkPoints) chunks, each with a
 // row of the frame's cells in the partial-count array.
+// Upper bound on the partial-count array of the chunked cell build (entries,
+// 4 bytes each); frames that would pass it count with global atomics instead.
+constexpr int64_t kMaxPartEntries = int64_t(1) << 27;
+
 void make_chunks(ConfigTables& T, const std::vector<int>& point_base, int nframes)
 {
     T.chunks.clear();
@@ -68,7 +72,7 @@ void make_chunks(ConfigTables& T, const std::vector<int>& point_base, int nframe
         F.chunk0 = (int)T.chunks.size();
         F.nchunks = 0;
         if (np == 0) continue;
-        if (nc > kChunkMaxCells) {
+        if (nc > kChunkMaxCells || T.part_entries + (int64_t)k * nc > kMaxPartEntries) {
             T.global_frames = true;
             continue;
         }
@@ -308,10 +312,6 @@ int ppa_batch_plan_create(int32_t n_frames, const ppa_box* boxes, const int64_t*
         T.cell_base[n_frames] = (int)cells;
         T.ncells = (int)cells;
         make_chunks(T, p->point_base, n_frames);
-        if (T.part_entries > 0x7fffffffLL) {
-            delete p;
-            return set_error(PPA_EINVAL, "too many cells in the batch");
-        }
     }
     Workspace W{};
     layout(p, nullptr, &W);

@@ -292,3 +292,29 @@ def test_batch_cell_build_chunking():
         assert L.ppa_batch_config_cells(h, 99, None, None, None) == ppa.PPA_EINVAL
     finally:
         L.ppa_batch_plan_destroy(h)
+
+
+def test_batch_chunk_table_budget():
+    """Chunked frames stop at a bounded partial-count array (2^27 entries):
+    the frames past it count with global atomics and the plan is still made
+    (host logic; no device work)."""
+    L = ppa.lib()
+    nf, npf = 72, 1 << 20
+    # a 19^3 box at r_max 0.6: 31^3 = 29791 cells for the first configuration,
+    # 64 chunks of 16384 points per frame
+    boxes = (ppa.CBox * nf)(*[ppa.Box((19.0, 19.0, 19.0), (0, 0, 0), 3).c() for _ in range(nf)])
+    off = (np.arange(nf + 1, dtype=np.int64) * npf)
+    h = ctypes.c_void_p()
+    assert L.ppa_batch_plan_create(nf, boxes, off.ctypes.data_as(ctypes.c_void_p), 32, 0.0, 0.6,
+                                   1, 0, ctypes.byref(h)) == 0
+    try:
+        c, k, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert L.ppa_batch_config_cells(h, 0, ctypes.byref(c), ctypes.byref(k),
+                                        ctypes.byref(g)) == 0
+        nc = c.value // nf
+        assert nc * nf == c.value and nc == 31 ** 3
+        chunked = (1 << 27) // (64 * nc)
+        assert (k.value, g.value) == (64 * chunked, nf - chunked)
+        assert 0 < chunked < nf
+    finally:
+        L.ppa_batch_plan_destroy(h)
