@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--only", choices=["pmft2d", "pmft3", "correlation", "steinhardt", "clusters",
                                        "batched", "smooth_rdf", "small"],
                     help="run one row alone and print its JSON (for profiling that row)")
+    ap.add_argument("--batch-config", type=int, default=None,
+                    help="batched row: after the autotuner has run, use this launch "
+                         "configuration instead of its pick (for counter runs, whose "
+                         "serialised dispatches can change the pick)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for "
                          "memory-traffic counters)")
@@ -621,7 +625,7 @@ def row_clusters(ppa, hip):
     return out
 
 
-def row_batched(ppa, hip):
+def row_batched(ppa, hip, force_config=None):
     import numpy as np
     import torch
 
@@ -637,6 +641,8 @@ def row_batched(ppa, hip):
     hist0, nl0 = plan.run(pts)  # sizes the per-frame outputs below
     total_pairs = nl0.n_pairs
     tune_ms, cfg = plan.autotune(pts, reps=2)
+    if force_config is not None:
+        cfg = plan.config(force_config)
     hist = torch.zeros((F, bins), dtype=torch.int64, device="cuda")
     launch = plan.graph(pts, hist)
     batched_ms = timed(launch, 5, warmup=1)
@@ -688,7 +694,7 @@ def row_batched(ppa, hip):
             "batched_pairs_per_s": total_pairs / (batched_ms * 1e-3),
             "per_frame_ms": per_frame_ms, "per_frame_frames_per_s": F / (per_frame_ms * 1e-3),
             "speedup": per_frame_ms / batched_ms,
-            "autotuned": cfg, "autotune_ms": tune_ms,
+            "autotuned": cfg, "autotune_ms": tune_ms, "config_forced": force_config,
             "note": "batched = one HIP-graph launch of the autotuned plan; per-frame = 256 eager "
                     "ppa_rdf calls with list, each building its own cell list"}
 
@@ -915,7 +921,7 @@ def main():
                "correlation": lambda: row_correlation(ppa, hip),
                "steinhardt": lambda: row_steinhardt(ppa, hip),
                "clusters": lambda: row_clusters(ppa, hip),
-               "batched": lambda: row_batched(ppa, hip),
+               "batched": lambda: row_batched(ppa, hip, args.batch_config),
                "smooth_rdf": lambda: row_smooth(ppa, hip),
                "small": lambda: row_small(ppa, hip)}
         print(json.dumps({"row": args.only, **fns[args.only]()}), flush=True)
@@ -944,7 +950,7 @@ def main():
             rows["correlation"]["lds_atomics_per_s"] / peak["256_bins_per_s"])
         rows["steinhardt"] = row_steinhardt(ppa, hip)
         rows["clusters"] = row_clusters(ppa, hip)
-        rows["batched"] = row_batched(ppa, hip)
+        rows["batched"] = row_batched(ppa, hip, args.batch_config)
         rows["smooth_rdf"] = row_smooth(ppa, hip)
         rows["small"] = row_small(ppa, hip)
         rows["paper_context"] = paper_context(ppa)
