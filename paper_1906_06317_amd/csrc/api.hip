@@ -540,7 +540,9 @@ int run_knn(const ppa_box* box, const float* pts, int64_t n, const float* qpts, 
 struct PmftPlan {
     Grid g;
     PmftTable table;
-    int words;   // LDS histogram words (0: global atomics)
+    int words;    // LDS histogram words (0: global atomics)
+    int entries;  // bins of the LDS histogram
+    int packed;   // two 16-bit counters per word
     int blocks;
 };
 
@@ -559,6 +561,8 @@ int pmft_plan(const BoxPrep& bp, int64_t n, int32_t nbx, int32_t nby, float x_ma
     // bins a bond shorter than r_max can reach: per row ix, the iy range
     // covering |y| < sqrt(r_max^2 - min|x|^2), widened by a bin each side
     P->words = 0;
+    P->entries = 0;
+    P->packed = 0;
     if (nbx <= kPmftMaxRows) {
         const double dx = 2.0 * x_max / nbx, dy = 2.0 * y_max / nby, r = r_max;
         int base = 0;
@@ -577,9 +581,22 @@ int pmft_plan(const BoxPrep& bp, int64_t n, int32_t nbx, int32_t nby, float x_ma
             base += hi - lo;
         }
         P->table.base[nbx] = base;
-        if ((size_t)base * sizeof(unsigned) <= pmft_lds_limit()) P->words = base;
+        // 32-bit counters, or two 16-bit counters per word when that is the
+        // only way to fit the LDS or lets more workgroups share a CU
+        const int half = (base + 1) / 2;
+        const bool fit32 = (size_t)base * sizeof(unsigned) <= pmft_lds_limit();
+        const bool fit16 = (size_t)half * sizeof(unsigned) <= pmft_lds_limit();
+        if (base > 0 && fit16) {
+            P->entries = base;
+            if (!fit32 || pmft_blocks_per_cu(half, 1) > pmft_blocks_per_cu(base, 0)) {
+                P->packed = 1;
+                P->words = half;
+            } else {
+                P->words = base;
+            }
+        }
     }
-    P->blocks = pmft_workgroups(P->words);
+    P->blocks = pmft_workgroups(P->words, P->packed);
     return PPA_OK;
 }
 
@@ -589,9 +606,9 @@ size_t pmft_layout(const PmftPlan& P, int64_t n, int64_t nq_sep, void* base_v, W
     char* base = (char*)base_v;
     size_t off = workspace_layout(P.g, n, nq_sep, 0, base_v, W);
     *partial = base ? (unsigned*)(base + off) : nullptr;
-    off = (off + sizeof(unsigned) * (size_t)P.blocks * (size_t)P.words + 255) & ~(size_t)255;
+    off = (off + sizeof(unsigned) * (size_t)P.blocks * (size_t)P.entries + 255) & ~(size_t)255;
     *level2 = base ? (unsigned*)(base + off) : nullptr;
-    off += sizeof(unsigned) * (size_t)partial_rows(P.blocks) * (size_t)P.words;
+    off += sizeof(unsigned) * (size_t)partial_rows(P.blocks) * (size_t)P.entries;
     return (off + 255) & ~(size_t)255;
 }
 
@@ -647,6 +664,8 @@ int run_pmft(const ppa_box* box, const float* pts, int64_t n, const float* qpts,
     A.inv_dx = (float)((double)nbx / (2.0 * x_max));
     A.inv_dy = (float)((double)nby / (2.0 * y_max));
     A.words = P.words;
+    A.entries = P.entries;
+    A.packed = P.packed;
     A.partial = partial;
     A.level2 = level2;
     A.counts = counts;

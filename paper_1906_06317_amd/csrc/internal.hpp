@@ -258,15 +258,18 @@ struct PmftArgs {
     float x_max, y_max;
     float inv_dx, inv_dy;     // bins per unit length
     int words;                // LDS words of the compacted histogram (0: global atomics)
-    unsigned* partial;        // [gridDim.x][words] per-workgroup histograms
-    unsigned* level2;         // [ceil(gridDim.x / 32)][words] first-stage sums
+    int entries;              // bins the compacted histogram holds
+    int packed;               // 1: two 16-bit counters per LDS word
+    unsigned* partial;        // [gridDim.x][entries] per-workgroup histograms
+    unsigned* level2;         // [ceil(gridDim.x / 32)][entries] first-stage sums
     unsigned* counts;         // [nbx * nby] accumulated
     PmftTable table;
 };
 
 // Returns the number of workgroups launched (partials needed), or a negative
 // PPA error when the launch failed.
-int pmft_workgroups(int words);
+int pmft_blocks_per_cu(int words, int packed);
+int pmft_workgroups(int words, int packed);
 size_t pmft_lds_limit();  // bytes of LDS a workgroup may give the histogram
 void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s);
 

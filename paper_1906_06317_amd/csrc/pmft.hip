@@ -15,10 +15,13 @@
 // histogram is privatised per workgroup in LDS, keeping only the bins a bond
 // shorter than r_max can reach (the paper notes that multi-dimensional
 // histograms outgrow the caches first): at 200 x 200 bins on [-3, 3)^2 with
-// r_max = 3 that is about 129 KB, so one 1024-thread workgroup per CU holds
-// it.  Each workgroup writes its histogram to its own partial array and a
-// second kernel sums the partials into the caller's counts, so no global
-// atomics are needed.  Histograms too large for LDS use global atomics.
+// r_max = 3 that is 31,450 bins.  When it lets more workgroups share a CU,
+// two 16-bit counters share an LDS word (63 KB instead of 126 KB there, two
+// 1024-thread workgroups per CU instead of one); a counter that reaches 2^15
+// hands 2^15 to the caller's count with one global atomic (the lane whose
+// add took it there), so a counter never wraps.  Each workgroup writes its
+// histogram to its own partial array and a second kernel sums the partials
+// into the caller's counts.  Histograms too large for LDS use global atomics.
 #include "pair_common.hpp"
 
 namespace ppa {
@@ -40,8 +43,12 @@ struct PmftLds {
 
 constexpr int kBondBuf = 2 * kWave;  // rotated bonds buffered per wavefront
 
+// Where the bins live: global atomics only, the LDS window with 32-bit
+// counters, or the LDS window with two 16-bit counters per word.
+enum { kHistGlobal = 0, kHistLds32 = 1, kHistLds16 = 2 };
+
 // Bins one rotated bond (the calling lanes).
-template <bool LDS>
+template <int MODE>
 __device__ __forceinline__ void bin_rotated(const PmftArgs& a, const PmftLds& L, unsigned* hist,
                                             float xr, float yr)
 {
@@ -50,11 +57,25 @@ __device__ __forceinline__ void bin_rotated(const PmftArgs& a, const PmftLds& L,
     if (!(tx >= 0.f && tx < (float)a.nbx && ty >= 0.f && ty < (float)a.nby)) return;
     const int ix = min((int)tx, a.nbx - 1);
     const int iy = min((int)ty, a.nby - 1);
-    if (LDS) {
+    if (MODE != kHistGlobal) {
         const int w = iy - L.lo[ix];
         const int b = L.base[ix];
         if (w >= 0 && w < L.base[ix + 1] - b) {
-            atomicAdd(&hist[b + w], 1u);
+            if (MODE == kHistLds32) {
+                atomicAdd(&hist[b + w], 1u);
+                return;
+            }
+            // entry e is the low (even e) or high half of word e / 2; the add
+            // that takes a half from 2^15 - 1 to 2^15 takes 2^15 back out and
+            // into the global count, so a half stays below 2^15 plus the adds
+            // in flight (fewer than a workgroup's lanes) and never wraps
+            const int e = b + w;
+            const unsigned sh = (unsigned)(e & 1) << 4;
+            const unsigned old = atomicAdd(&hist[e >> 1], 1u << sh);
+            if (((old >> sh) & 0xffffu) == 0x7fffu) {
+                atomicSub(&hist[e >> 1], 0x8000u << sh);
+                atomicAdd(&a.counts[ix * a.nby + iy], 0x8000u);
+            }
             return;
         }
     }
@@ -62,7 +83,7 @@ __device__ __forceinline__ void bin_rotated(const PmftArgs& a, const PmftLds& L,
 }
 
 // A wavefront's buffer of rotated bonds waiting to be binned.
-template <bool LDS>
+template <int MODE>
 struct BondBuf {
     float2* buf;  // [kBondBuf] in LDS
     int nb;       // bonds buffered
@@ -86,14 +107,14 @@ struct BondBuf {
         wave_sync();
         if (more) buf[lane] = rest;
         nb -= kWave;
-        bin_rotated<LDS>(a, L, hist, v.x, v.y);
+        bin_rotated<MODE>(a, L, hist, v.x, v.y);
     }
     __device__ __forceinline__ void finish(const PmftArgs& a, const PmftLds& L, unsigned* hist)
     {
         wave_sync();
         if (lane < nb) {
             const float2 v = buf[lane];
-            bin_rotated<LDS>(a, L, hist, v.x, v.y);
+            bin_rotated<MODE>(a, L, hist, v.x, v.y);
         }
         nb = 0;
         wave_sync();
@@ -102,9 +123,9 @@ struct BondBuf {
 
 // The queries of one home cell against candidates [k0, k0 + 64 NS) of its
 // stencil.
-template <int NS, bool LDS>
+template <int NS, int MODE>
 __device__ __forceinline__ void pmft_tile(const PmftArgs& a, const PairIn& in, const PmftLds& L,
-                                          const StencilLds& S, unsigned* hist, BondBuf<LDS>& B,
+                                          const StencilLds& S, unsigned* hist, BondBuf<MODE>& B,
                                           int C, int k0, int q0, int q1, int lane)
 {
     const PairGeom& G = a.geom;
@@ -135,16 +156,17 @@ __device__ __forceinline__ void pmft_tile(const PmftArgs& a, const PairIn& in, c
     }
 }
 
-template <bool LDS>
+template <int MODE>
 __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
 {
+    constexpr bool LDS = MODE != kHistGlobal;
     extern __shared__ unsigned s_hist[];
     __shared__ PmftLds L;
     __shared__ float2 s_bonds[kPmftWaves][kBondBuf];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = uniform(threadIdx.x / kWave);
     const PairGeom& G = a.geom;
-    BondBuf<LDS> B{s_bonds[wv], 0, lane};
+    BondBuf<MODE> B{s_bonds[wv], 0, lane};
     if (threadIdx.x < 9)
         L.off[threadIdx.x] = make_float4(G.off[threadIdx.x][0], G.off[threadIdx.x][1], 0.f, 0.f);
     if (LDS) {
@@ -165,19 +187,27 @@ __global__ void __launch_bounds__(kPmftBlock) pmft_kernel(const PmftArgs a)
         const int ns = (C + kWave - 1) / kWave;
         switch (ns) {
 #define PPA_CASE(N) \
-    case N: pmft_tile<N, LDS>(a, in, L, S, s_hist, B, C, 0, q0, q1, lane); break;
+    case N: pmft_tile<N, MODE>(a, in, L, S, s_hist, B, C, 0, q0, q1, lane); break;
             PPA_CASE(0) PPA_CASE(1) PPA_CASE(2) PPA_CASE(3) PPA_CASE(4)
 #undef PPA_CASE
         default:
             for (int k0 = 0; k0 < C; k0 += kPmftChunk * kWave)
-                pmft_tile<kPmftChunk, LDS>(a, in, L, S, s_hist, B, C, k0, q0, q1, lane);
+                pmft_tile<kPmftChunk, MODE>(a, in, L, S, s_hist, B, C, k0, q0, q1, lane);
         }
     }
     B.finish(a, L, s_hist);
     if (LDS) {
         __syncthreads();
-        unsigned* out = a.partial + (size_t)blockIdx.x * a.words;
-        for (int i = threadIdx.x; i < a.words; i += kPmftBlock) out[i] = s_hist[i];
+        unsigned* out = a.partial + (size_t)blockIdx.x * a.entries;
+        if (MODE == kHistLds32) {
+            for (int i = threadIdx.x; i < a.words; i += kPmftBlock) out[i] = s_hist[i];
+        } else {
+            for (int i = threadIdx.x; i < a.words; i += kPmftBlock) {
+                const unsigned v = s_hist[i];
+                out[2 * i] = v & 0xffffu;
+                if (2 * i + 1 < a.entries) out[2 * i + 1] = v >> 16;
+            }
+        }
     }
 }
 
@@ -201,20 +231,30 @@ __global__ void __launch_bounds__(256) pmft_reduce_kernel(const unsigned* __rest
 
 }  // namespace
 
-// Workgroups of the LDS-histogram launch (one per CU when the histogram
-// fills most of the LDS), or of the global-atomics launch; a multiple of 8.
-int pmft_workgroups(int words)
+// Resident workgroups per CU of the launch with `words` LDS words of
+// histogram (0: the global-atomics kernel), 32- or 16-bit counters.
+int pmft_blocks_per_cu(int words, int packed)
 {
-    const int cus = device_cus();
     const size_t lds = sizeof(unsigned) * (size_t)words;
     int per_cu = 0;
-    hipError_t e = words > 0
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<true>,
-                                                                      kPmftBlock, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<false>,
-                                                                      kPmftBlock, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    return (cus * per_cu + 7) / 8 * 8;
+    hipError_t e;
+    if (words <= 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<kHistGlobal>,
+                                                         kPmftBlock, 0);
+    else if (packed)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<kHistLds16>,
+                                                         kPmftBlock, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmft_kernel<kHistLds32>,
+                                                         kPmftBlock, lds);
+    return e != hipSuccess || per_cu < 1 ? 1 : per_cu;
+}
+
+// Workgroups of the LDS-histogram launch (as many as are resident at once),
+// or of the global-atomics launch; a multiple of 8.
+int pmft_workgroups(int words, int packed)
+{
+    return (device_cus() * pmft_blocks_per_cu(words, packed) + 7) / 8 * 8;
 }
 
 size_t pmft_lds_limit()
@@ -237,17 +277,19 @@ void launch_pmft(const PmftArgs& a, int blocks, hipStream_t s)
 {
     if (a.words > 0) {
         const size_t lds = sizeof(unsigned) * (size_t)a.words;
-        (void)hipFuncSetAttribute((const void*)pmft_kernel<true>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(pmft_kernel<true>, dim3(blocks), dim3(kPmftBlock), lds, s, a);
+        const auto k = a.packed ? pmft_kernel<kHistLds16> : pmft_kernel<kHistLds32>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(kPmftBlock), lds, s, a);
         const int rows = partial_rows(blocks);
-        hipLaunchKernelGGL(partial_sum_stage1<unsigned>, dim3((a.words + 63) / 64, rows),
-                           dim3(256), 0, s, a.partial, blocks, a.words, kPartialRowsPer, a.level2);
+        hipLaunchKernelGGL(partial_sum_stage1<unsigned>, dim3((a.entries + 63) / 64, rows),
+                           dim3(256), 0, s, a.partial, blocks, a.entries, kPartialRowsPer,
+                           a.level2);
         const int nb = a.nbx * a.nby;
         hipLaunchKernelGGL(pmft_reduce_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.level2,
-                           rows, a.words, a.nbx, a.nby, a.table, a.counts);
+                           rows, a.entries, a.nbx, a.nby, a.table, a.counts);
     } else {
-        hipLaunchKernelGGL(pmft_kernel<false>, dim3(blocks), dim3(kPmftBlock), 0, s, a);
+        hipLaunchKernelGGL(pmft_kernel<kHistGlobal>, dim3(blocks), dim3(kPmftBlock), 0, s, a);
     }
 }
 

@@ -86,11 +86,37 @@ def test_separate_query_points(ppa, exclude_ii):
     _compare(ppa, s, th, 50, 50, 3.0, 3.0, 3.0, query=(q, qth), exclude_ii=exclude_ii)
 
 
-@pytest.mark.parametrize("nb", [300, 256])
-def test_histograms_beyond_lds_use_global_atomics(ppa, nb):
+@pytest.mark.parametrize("nb", [256, 300, 400])
+def test_large_histograms(ppa, nb):
+    """256 x 256 fits the LDS only as 16-bit counters; 300 x 300 and beyond
+    go to global atomics (no per-workgroup partial histograms)."""
     s, th = _fluid(3000, 0.7, 12)
-    assert ppa.pmft2d_workspace_bytes(_box(s), 3000, 0, nb, nb, 3.0, 3.0, 3.0) < 50 << 20
+    ws = ppa.pmft2d_workspace_bytes(_box(s), 3000, 0, nb, nb, 3.0, 3.0, 3.0)
+    if nb >= 300:
+        assert ws < 50 << 20
+    else:
+        assert ws > 50 << 20
     _compare(ppa, s, th, nb, nb, 3.0, 3.0, 3.0)
+
+
+def test_dense_cluster_counters_hand_over(ppa):
+    """6000 points in a disc of radius 0.05: one home cell makes all 36 M
+    bonds, and the bins near the origin each collect far more than 2^16 of
+    them inside one workgroup, so a 16-bit LDS counter must hand 2^15 at a
+    time to the global count (200 x 200 bins on [-3, 3)^2, the window that
+    takes two 16-bit counters per word)."""
+    rng = np.random.default_rng(17)
+    n = 6000
+    rad = 0.05 * np.sqrt(rng.uniform(0, 1, n))
+    phi = rng.uniform(0, 2 * math.pi, n)
+    pts = np.zeros((n, 3), np.float32)
+    pts[:, 0] = rad * np.cos(phi)
+    pts[:, 1] = rad * np.sin(phi)
+    s = workloads.System((10.0, 10.0, 1.0), (0.0, 0.0, 0.0), 2, pts)
+    th = rng.uniform(0.0, 2 * math.pi, n).astype(np.float32)
+    g, lo, hi, amb = _compare(ppa, s, th, 200, 200, 3.0, 3.0, 3.0)
+    assert int(g.max()) > 1 << 17
+    assert int(g.astype(np.int64).sum()) == n * (n - 1)
 
 
 def test_counts_accumulate(ppa):
