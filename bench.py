@@ -514,9 +514,24 @@ def row_pmft(ppa, hip):
     if ws.status() != 0:
         raise RuntimeError(L.ppa_last_error().decode())
     pairs = int(counts.to(torch.int64).sum().item()) // 12
+    # the same call at other bin counts: the LDS window with 32-bit counters
+    # (100), with two 16-bit counters per word (256), global atomics (300)
+    by_bins = {}
+    for nb in (100, 256, 300):
+        wp, wl = ws.get(ppa.pmft2d_workspace_bytes(box, n, 0, nb, nb, 3.0, 3.0, 3.0))
+        c = torch.zeros(nb * nb, dtype=torch.int32, device="cuda")
+
+        def call_nb():
+            rc = L.ppa_pmft2d(ctypes.byref(cb), p(pts), n, None, p(th), n, nb, nb, 3.0, 3.0, 3.0,
+                              1, 0, wp, wl, p(c), sptr)
+            if rc != 0:
+                raise RuntimeError(L.ppa_last_error().decode())
+        by_bins[f"{nb}x{nb}"] = timed(call_nb, 5, warmup=1)
+    if ws.status() != 0:
+        raise RuntimeError(L.ppa_last_error().decode())
     return {"workload": "2D fluid N=262,144, density 0.7, r_max=3, 200x200 bins on [-3,3)^2",
             "ms": ms, "binning_kernels_ms": kern, "pairs": pairs,
-            "pairs_per_s": pairs / (ms * 1e-3)}
+            "pairs_per_s": pairs / (ms * 1e-3), "ms_by_bins": by_bins}
 
 
 def row_correlation(ppa, hip):
