@@ -94,12 +94,12 @@ struct KnnSlots {
     __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
                                          const float4* off, int C, int lane)
     {
+        int before = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             x[s] = y[s] = z[s] = kFar;
             id[s] = -1;
-            const int k = s * kWave + lane;
-            if (k < C) fetch<DIM>(in, G, S, off, k, x[s], y[s], z[s], id[s]);
+            fetch_slot<DIM>(in, G.nsten, S, off, 0, s, C, lane, before, x[s], y[s], z[s], id[s]);
         }
     }
 };

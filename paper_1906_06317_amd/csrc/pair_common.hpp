@@ -89,6 +89,12 @@ struct PairIn {
 struct StencilLds {
     int pre[32];
     int start[32];
+    // candidate k's stencil cell without a search: bit p of mask[p / 64]
+    // marks a non-empty cell whose candidates start at p (for p below
+    // kMaxSlots * 64), and jrank[r] is the r-th non-empty cell, so k lies in
+    // cell jrank[(set bits at or below k) - 1]
+    unsigned long long mask[kMaxSlots];
+    unsigned char jrank[32];
 };
 
 // Home cells of this wavefront: [t0, t1).  Workgroups are renumbered so the
@@ -204,6 +210,15 @@ __device__ __forceinline__ int stencil(const PairIn& in, int n0, int n1, int n2,
         S.start[lane] = st;
     }
     if (lane == 0) S.pre[0] = 0;
+    if (lane < kMaxSlots) S.mask[lane] = 0ull;
+    wave_sync();
+    const bool nonempty = lane < nsten && cnt > 0;
+    const unsigned long long ne = __ballot(nonempty);
+    if (nonempty) {
+        const int p = incl - cnt;
+        S.jrank[lane_prefix(ne)] = (unsigned char)lane;
+        if (p < kMaxSlots * kWave) atomicOr(&S.mask[p >> 6], 1ull << (p & 63));
+    }
     wave_sync();
     return uniform(__shfl(incl, nsten - 1));
 }
@@ -215,30 +230,47 @@ __device__ __forceinline__ int stencil(const PairIn& in, const PairGeom& G, int 
     return stencil<DIM>(in, G.n[0], G.n[1], G.n[2], G.nsten, 0, tile, lane, S);
 }
 
-// Candidate at flat stencil index k, relative to the home cell's centre.
-template <int DIM>
-__device__ __forceinline__ void fetch(const PairIn& in, int nsten, const StencilLds& S,
-                                      const float4* off, int k, float& x, float& y, float& z,
-                                      int& id)
+// Stencil cell of candidate k = k0 + 64 s + lane of a stencil walk (for
+// k < C; 0 otherwise).  A walk from the stencil's first candidate reads slot
+// s's start mask: k lies in the non-empty cell whose start is the last set
+// bit at or below k, counted with `before`, the non-empty cells starting in
+// earlier slots (which the call advances).  Other walks (a chunk that starts
+// further in, or slots past the masks) search the prefix counts.
+__device__ __forceinline__ int cell_of(const StencilLds& S, int nsten, int k0, int s, int k,
+                                       int C, int& before)
 {
     int j = 0;
+    if (k0 == 0 && s < kMaxSlots) {
+        const unsigned long long m = uniform64(S.mask[s]);
+        // set bits of m at or below this lane: bit 0, then the mbcnt of m >> 1
+        if (k < C) j = S.jrank[lane_slot(m >> 1, before + (int)(m & 1ull) - 1)];
+        before += __popcll(m);
+    } else if (k < C) {
 #pragma unroll
-    for (int step = 16; step > 0; step >>= 1)
-        if (j + step < nsten && S.pre[j + step] <= k) j += step;
-    const float4 v = in.cand[S.start[j] + (k - S.pre[j])];
-    const float4 o = off[j];
-    x = v.x + o.x;
-    y = v.y + o.y;
-    z = DIM == 3 ? v.z + o.z : 0.f;
-    id = __float_as_int(v.w);
+        for (int step = 16; step > 0; step >>= 1)
+            if (j + step < nsten && S.pre[j + step] <= k) j += step;
+    }
+    return j;
 }
 
+// Fills slot s (candidates k0 + 64 s + lane) of a register-slot load with
+// the candidate relative to the home cell's centre; entries past C are left
+// as they are.
 template <int DIM>
-__device__ __forceinline__ void fetch(const PairIn& in, const PairGeom& G, const StencilLds& S,
-                                      const float4* off, int k, float& x, float& y, float& z,
-                                      int& id)
+__device__ __forceinline__ void fetch_slot(const PairIn& in, int nsten, const StencilLds& S,
+                                           const float4* off, int k0, int s, int C, int lane,
+                                           int& before, float& x, float& y, float& z, int& id)
 {
-    fetch<DIM>(in, G.nsten, S, off, k, x, y, z, id);
+    const int k = k0 + s * kWave + lane;
+    const int j = cell_of(S, nsten, k0, s, k, C, before);
+    if (k < C) {
+        const float4 v = in.cand[S.start[j] + (k - S.pre[j])];
+        const float4 o = off[j];
+        x = v.x + o.x;
+        y = v.y + o.y;
+        z = DIM == 3 ? v.z + o.z : 0.f;
+        id = __float_as_int(v.w);
+    }
 }
 
 // What the pair loops need of a frame's geometry (one frame, or the frame of
@@ -304,12 +336,12 @@ struct Slots {
     __device__ __forceinline__ void load(const PairIn& in, int nsten, const StencilLds& S,
                                          const float4* off, int k0, int C, int lane)
     {
+        int before = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             x[s] = y[s] = z[s] = kFar;
             id[s] = -1;
-            const int k = k0 + s * kWave + lane;
-            if (k < C) fetch<DIM>(in, nsten, S, off, k, x[s], y[s], z[s], id[s]);
+            fetch_slot<DIM>(in, nsten, S, off, k0, s, C, lane, before, x[s], y[s], z[s], id[s]);
             cc[s] = dist2<DIM>(x[s], y[s], z[s]);
         }
     }
@@ -348,12 +380,12 @@ struct DotSlots {
     __device__ __forceinline__ void load(const PairIn& in, int nsten, const StencilLds& S,
                                          const float4* off, int k0, int C, int lane)
     {
+        int before = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             float x = kFar, y = kFar, z = kFar;
             id[s] = -1;
-            const int k = k0 + s * kWave + lane;
-            if (k < C) fetch<DIM>(in, nsten, S, off, k, x, y, z, id[s]);
+            fetch_slot<DIM>(in, nsten, S, off, k0, s, C, lane, before, x, y, z, id[s]);
             cc[s] = dist2<DIM>(x, y, z);
             mx[s] = -2.f * x;
             my[s] = -2.f * y;

@@ -59,17 +59,15 @@ struct SmSlots {
     __device__ __forceinline__ void load(const PairIn& in, const PairGeom& G, const StencilLds& S,
                                          const float4* off, int k0, int C, int lane)
     {
+        int before = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             x[s] = y[s] = z[s] = kFar;
             idx[s] = -1;
             j[s] = 0;
             const int k = k0 + s * kWave + lane;
+            const int jj = cell_of(S, G.nsten, k0, s, k, C, before);
             if (k < C) {
-                int jj = 0;
-#pragma unroll
-                for (int step = 16; step > 0; step >>= 1)
-                    if (jj + step < G.nsten && S.pre[jj + step] <= k) jj += step;
                 const int p = S.start[jj] + (k - S.pre[jj]);
                 const float4 v = in.cand[p];
                 const float4 o = off[jj];
