@@ -87,8 +87,8 @@ struct PairIn {
 };
 
 struct StencilLds {
-    int pre[32];
-    int start[32];
+    int pre[32];   // candidates in the cells before stencil slot j
+    int base[32];  // first sorted position of slot j's cell, less pre[j]
     // candidate k's stencil cell without a search: bit p of mask[p / 64]
     // marks a non-empty cell whose candidates start at p (for p below
     // kMaxSlots * 64), and jrank[r] is the r-th non-empty cell, so k lies in
@@ -207,7 +207,7 @@ __device__ __forceinline__ int stencil(const PairIn& in, int n0, int n1, int n2,
     }
     if (lane < nsten) {
         S.pre[lane + 1] = incl;
-        S.start[lane] = st;
+        S.base[lane] = st - (incl - cnt);
     }
     if (lane == 0) S.pre[0] = 0;
     if (lane < kMaxSlots) S.mask[lane] = 0ull;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void fetch_slot(const PairIn& in, int nsten, const St
     const int k = k0 + s * kWave + lane;
     const int j = cell_of(S, nsten, k0, s, k, C, before);
     if (k < C) {
-        const float4 v = in.cand[S.start[j] + (k - S.pre[j])];
+        const float4 v = in.cand[S.base[j] + k];
         const float4 o = off[j];
         x = v.x + o.x;
         y = v.y + o.y;

@@ -68,7 +68,7 @@ struct SmSlots {
             const int k = k0 + s * kWave + lane;
             const int jj = cell_of(S, G.nsten, k0, s, k, C, before);
             if (k < C) {
-                const int p = S.start[jj] + (k - S.pre[jj]);
+                const int p = S.base[jj] + k;
                 const float4 v = in.cand[p];
                 const float4 o = off[jj];
                 x[s] = v.x + o.x;
