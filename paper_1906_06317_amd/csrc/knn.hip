@@ -204,8 +204,8 @@ __device__ __forceinline__ void knn_tile(const KnnArgs& a, const PairIn& in, con
                 r += (a2.x < mine ? 1 : 0) + (a2.y < mine ? 1 : 0) + (b2.x < mine ? 1 : 0) +
                      (b2.y < mine ? 1 : 0);
             }
-            if (gsz <= 32) r += __shfl_xor(r, 32);
-            if (gsz <= 16) r += __shfl_xor(r, 16);
+            if (gsz <= 32) r = pair_sum32(r);
+            if (gsz <= 16) r = pair_sum16(r);
             const int len = state == kRowFull ? k : cnt;
             if (lane < cnt && r < len) {
                 const long long o = (long long)k * qid + r;

@@ -55,6 +55,32 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Inclusive prefix sum over the wavefront by DPP: shifts by 1, 2, 4 and 8
+// lanes within each 16-lane row, then lane 15 of each even row added to the
+// row above and lane 31 to the upper half (vector instructions only).
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
+// x + x of lane l ^ 16 (one permlane16 swap), and of lane l ^ 32.
+__device__ __forceinline__ int pair_sum16(int x)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (int)r[0] + (int)r[1];
+}
+__device__ __forceinline__ int pair_sum32(int x)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (int)r[0] + (int)r[1];
+}
+
 __device__ __forceinline__ long long lane_of64(long long v, int t)
 {
     const unsigned lo = (unsigned)lane_of((int)(unsigned)v, t);
@@ -199,12 +225,7 @@ __device__ __forceinline__ int stencil(const PairIn& in, int n0, int n1, int n2,
         st = in.cand_start[nc];
         cnt = in.cand_start[nc + 1] - st;
     }
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-    }
+    const int incl = wave_incl_scan(cnt);
     if (lane < nsten) {
         S.pre[lane + 1] = incl;
         S.base[lane] = st - (incl - cnt);
@@ -220,7 +241,7 @@ __device__ __forceinline__ int stencil(const PairIn& in, int n0, int n1, int n2,
         if (p < kMaxSlots * kWave) atomicOr(&S.mask[p >> 6], 1ull << (p & 63));
     }
     wave_sync();
-    return uniform(__shfl(incl, nsten - 1));
+    return lane_of(incl, nsten - 1);
 }
 
 template <int DIM>
